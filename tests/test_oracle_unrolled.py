@@ -1,0 +1,114 @@
+"""Pins of the oracle's unrolled (trainable) decoder and its gradient.
+
+* With every scale at 0.9375 the unrolled forward equals plain T-iteration
+  BP of eq. (1) (bit-exact in FP32 and FP64).
+* N = 2 closed forms: R(1, column 2) = y1 + aR * y0 in the last iteration,
+  so d/d aR = y0, d/d y0 = aR, d/d y1 = 1 and every other scale has zero
+  gradient.
+* Central finite differences of the FP64 forward (h = 1e-4), with kinks of
+  the min screened out by comparing against a half step.
+"""
+
+import numpy as np
+import pytest
+
+import oracle
+from helpers import frozen_mask, make_frames
+
+
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+@pytest.mark.parametrize("N,K,T", [(8, 4, 3), (64, 32, 5), (128, 64, 20),
+                                   (1024, 512, 4)])
+def test_unrolled_at_default_scale_equals_plain_bp(prec, N, K, T):
+    m = N.bit_length() - 1
+    fz = frozen_mask(N, K)
+    _, _, llr = make_frames(N, K, 20, 2.0, stream=71)
+    alpha = np.full((T, m, 2), 0.9375)
+    out = oracle.unrolled_forward(llr, fz, alpha, prec=prec)
+    ref = oracle.decode(llr, fz, max_iter=T, early_stop=False, soft=True,
+                        prec=prec)
+    info = fz == 0
+    assert np.array_equal(out[:, info], ref["soft"][:, info])
+
+
+def test_n2_gradient_closed_form():
+    rng = np.random.default_rng(3)
+    y = rng.standard_normal((50, 2)).astype(np.float32) * 2
+    fz = np.array([1, 0], np.uint8)
+    T = 4
+    alpha = rng.uniform(0.5, 1.2, size=(T, 1, 2))
+    out = oracle.unrolled_forward(y, fz, alpha)
+    aR = alpha[T - 1, 0, 1]
+    y0 = y[:, 0].astype(np.float64)
+    assert np.allclose(out[:, 1], y[:, 1] + aR * y0, rtol=1e-15, atol=0)
+    dout = np.zeros((50, 2))
+    dout[:, 1] = rng.standard_normal(50)
+    da, dl = oracle.unrolled_grad(y, fz, alpha, dout)
+    want = np.zeros_like(da)
+    want[T - 1, 0, 1] = np.sum(dout[:, 1] * y0)
+    assert np.allclose(da, want, rtol=1e-13, atol=1e-13)
+    assert np.allclose(dl[:, 1], dout[:, 1], rtol=1e-15)
+    assert np.allclose(dl[:, 0], dout[:, 1] * aR, rtol=1e-15)
+
+
+def _fd_check(N, K, T, B, seed):
+    m = N.bit_length() - 1
+    fz = frozen_mask(N, K)
+    _, _, llr = make_frames(N, K, B, 1.5, stream=seed)
+    rng = np.random.default_rng(seed)
+    alpha = rng.uniform(0.7, 1.1, size=(T, m, 2))
+    dout = rng.standard_normal((B, N)) * (fz == 0)
+
+    def loss(a):
+        return float(np.sum(dout * oracle.unrolled_forward(llr, fz, a)))
+
+    da, _ = oracle.unrolled_grad(llr, fz, alpha, dout)
+    h = 1e-4
+    checked = 0
+    for idx in np.ndindex(alpha.shape):
+        e = np.zeros_like(alpha)
+        e[idx] = h
+        fd1 = (loss(alpha + e) - loss(alpha - e)) / (2 * h)
+        fd2 = (loss(alpha + e / 2) - loss(alpha - e / 2)) / h
+        if abs(fd1 - fd2) > 1e-6 * max(1.0, abs(fd1)):
+            continue                    # a min switched inside the step
+        checked += 1
+        assert abs(da[idx] - fd1) <= 1e-6 * max(1.0, abs(fd1)), idx
+    return checked, alpha.size
+
+
+@pytest.mark.parametrize("N,K,T,B", [(8, 4, 3, 4), (16, 8, 4, 3), (64, 32, 3, 2)])
+def test_alpha_gradient_matches_central_differences(N, K, T, B):
+    checked, total = _fd_check(N, K, T, B, seed=80 + N)
+    assert checked >= 0.8 * total
+
+
+def test_llr_gradient_matches_central_differences():
+    N, K, T, B = 16, 8, 4, 2
+    m = 4
+    fz = frozen_mask(N, K)
+    _, _, llr = make_frames(N, K, B, 1.5, stream=91)
+    llr = llr.astype(np.float64)
+    rng = np.random.default_rng(91)
+    alpha = rng.uniform(0.7, 1.1, size=(T, m, 2))
+    dout = rng.standard_normal((B, N)) * (fz == 0)
+    _, dl = oracle.unrolled_grad(llr.astype(np.float32), fz, alpha, dout)
+    # the forward takes FP32 LLRs, so differentiate with a step that FP32
+    # represents exactly around each value
+    checked = 0
+    for f in range(B):
+        for i in range(N):
+            x = np.float32(llr[f, i])
+            h = np.float32(2.0 ** (np.floor(np.log2(abs(x) + 1e-30)) - 12))
+            vals = []
+            for s in (h, -h, h / 2, -h / 2):
+                l2 = llr.astype(np.float32).copy()
+                l2[f, i] = x + s
+                vals.append(float(np.sum(dout * oracle.unrolled_forward(l2, fz, alpha))))
+            fd1 = (vals[0] - vals[1]) / (2 * float(h))
+            fd2 = (vals[2] - vals[3]) / float(h)
+            if abs(fd1 - fd2) > 1e-6 * max(1.0, abs(fd1)):
+                continue
+            checked += 1
+            assert abs(dl[f, i] - fd1) <= 1e-5 * max(1.0, abs(fd1)), (f, i)
+    assert checked >= 0.8 * B * N
