@@ -1,0 +1,217 @@
+"""Throughput of the polar BP decoder on one MI355X.
+
+Workload: the (1024, 512) polar code (design Eb/N0 0 dB), BPSK over AWGN at
+Eb/N0 = 3.0 dB, scaled min-sum with alpha = 0.9375, at most 40 iterations,
+G-matrix early stop plus CSFG freezing (eq. (2) on the total belief, one
+freeze per iteration).  A step decodes one batch of frames already resident
+in device memory; the metric is decoded information bits per second.
+
+Prints one JSON line.  Beside the headline it reports: PE activations per
+frame; the same batch under 40-iteration BP and under early stop alone
+(speed-up and error-rate match); the decoder kernel's fraction of the VALU
+roofline; and the CPU oracle timed on the host's cores on a bounded sample.
+"""
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = ("decoded info Mbit/s at N=1024 R=1/2 3.0dB, FER-matched; "
+          "PE updates/frame")
+
+# VALU roofline of gfx950 without packed FP32: 256 CUs x 64 lanes x 2.4 GHz
+# 32-bit lane operations per second; eq. (1) costs 12 operations per PE
+# activation (3 adds, 3 magnitude minima, 3 scalings, 3 sign products).
+VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
+OPS_PER_PE = 12
+
+MODES = {
+    "es_frz": dict(early_stop=True, freezing=True, freeze_input=1, freeze_walk=0),
+    "es": dict(early_stop=True, freezing=False),
+    "plain": dict(early_stop=False, freezing=False),
+}
+
+
+def wilson(k, n, z):
+    p = k / n
+    d = 1 + z * z / n
+    c = (p + z * z / (2 * n)) / d
+    h = z * np.sqrt(p * (1 - p) / n + z * z / (4 * n * n)) / d
+    return c - h, c + h
+
+
+def make_inputs(pbp, torch, code, frozen, N, K, B, ebn0, stream):
+    """Seeded info bits and noise (host), encoding on the device, channel
+    LLRs (host, FP64 rounded once), uploaded to device memory."""
+    import synth
+    info = synth.info_bits(K, B, stream=stream)
+    d_info = torch.from_numpy(info).cuda()
+    cw = pbp.pbp_encode(code, d_info)
+    torch.cuda.synchronize()
+    noise = synth.normals(N, B, stream=stream)
+    llr = synth.channel_llr(cw.cpu().numpy(), noise, ebn0, K / N)
+    del noise
+    return info, torch.from_numpy(llr).cuda()
+
+
+def time_mode(pbp, torch, code, d_llr, opts, steps, warmup):
+    out = pbp.pbp_decode(code, d_llr, **opts)
+    torch.cuda.synchronize()
+    for _ in range(warmup):
+        pbp.pbp_decode(code, d_llr, out=out, **opts)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    for _ in range(steps):
+        pbp.pbp_decode(code, d_llr, out=out, **opts)
+    ev1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = ev0.elapsed_time(ev1) / steps
+    return ms, wall, {k: v.cpu().numpy() for k, v in out.items()}
+
+
+def cpu_baseline(llr, frozen, info_ref, opts, K, seconds):
+    """The FP32 oracle on the host's cores over a bounded sample of the same
+    frames, in chunks, until the time budget is spent."""
+    import threading
+    from concurrent.futures import ThreadPoolExecutor
+
+    import oracle
+    threads = max(1, min(16, os.cpu_count() or 1))
+    chunk = 16
+    nxt = [0]
+    lock = threading.Lock()
+    done = []
+    t0 = time.perf_counter()
+    deadline = t0 + seconds
+
+    def worker():
+        while time.perf_counter() < deadline:
+            with lock:
+                lo = nxt[0]
+                if lo >= len(llr):
+                    return
+                nxt[0] += chunk
+            r = oracle.decode(llr[lo:lo + chunk], frozen, **opts)
+            done.append((lo, r["info"]))
+
+    with ThreadPoolExecutor(threads) as ex:
+        for f in [ex.submit(worker) for _ in range(threads)]:
+            f.result()
+    wall = time.perf_counter() - t0
+    frames = sum(len(i) for _, i in done)
+    mism = sum(int(np.sum(np.any(i != info_ref[lo:lo + len(i)], axis=1)))
+               for lo, i in done)
+    return {"value": frames * K / wall / 1e6, "unit": "Mbit/s",
+            "cores": threads, "kind": "oracle",
+            "sample": f"{frames} frames of the timed batch, FP32 oracle, "
+                      f"{threads} threads, {wall:.1f} s",
+            "frames": frames, "gpu_mismatches": mism}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--batch", type=int, default=1 << 16)
+    ap.add_argument("--ebn0", type=float, default=3.0)
+    ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-reference-modes", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported "
+              "(frames are independent: a multi-GPU run would shard the batch "
+              "by frame and only sum counters)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_1505_04979_amd as pbp
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+
+    N, K, B, max_iter, alpha = 1024, 512, args.batch, 40, 0.9375
+    frozen = pbp.pbp_construct(N, K, 0.0)
+    code = pbp.Code(N, K, frozen)
+    t0 = time.perf_counter()
+    info, d_llr = make_inputs(pbp, torch, code, frozen, N, K, B, args.ebn0,
+                              stream=(2 << 16) + 5)
+    gen_s = time.perf_counter() - t0
+
+    res = {}
+    for name in (["es_frz"] if args.no_reference_modes else ["es_frz", "es", "plain"]):
+        opts = dict(MODES[name], max_iter=max_iter, alpha=alpha)
+        steps = args.steps if name == "es_frz" else max(1, args.steps // 3)
+        ms, wall, out = time_mode(pbp, torch, code, d_llr, opts, steps,
+                                  args.warmup if name == "es_frz" else 1)
+        errs = int(np.sum(np.any(out["info"] != info, axis=1)))
+        res[name] = dict(ms=ms, wall=wall, steps=steps, errors=errs,
+                         fer=errs / B, iters=float(out["iters"].mean()),
+                         pe=float(out["pe"].mean()),
+                         mbps=B * K / (ms / 1e3) / 1e6, info=out["info"])
+
+    h = res["es_frz"]
+    line = {
+        "metric": METRIC,
+        "value": round(h["mbps"], 2),
+        "unit": "Mbit/s",
+        "n_gpus": 1,
+        "steps": h["steps"],
+        "warmup": args.warmup,
+        "ms_per_step": round(h["ms"], 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "polar BP decode, (1024,512) code, BPSK/AWGN "
+                               f"Eb/N0 {args.ebn0} dB, early stop + CSFG "
+                               "freezing",
+                   "N": N, "K": K, "ebn0_db": args.ebn0,
+                   "frames_per_step": B, "max_iter": max_iter, "alpha": alpha,
+                   "freeze_input": "total", "freeze_walk": "one_per_iter"},
+        "pe_per_frame": round(h["pe"], 1),
+        "avg_iters": round(h["iters"], 3),
+        "fer": h["fer"],
+    }
+    pe_total = h["pe"] * B
+    achieved = OPS_PER_PE * pe_total / (h["ms"] / 1e3) / 1e12
+    line["roofline"] = {"bound": "alu", "achieved": round(achieved, 3),
+                        "peak": round(VALU_PEAK_TOPS, 3), "unit": "TOP/s",
+                        "frac": round(achieved / VALU_PEAK_TOPS, 4),
+                        "traffic": None,
+                        "kernel": "bp_decode_kernel<10>",
+                        "kernel_ms": round(h["ms"], 4)}
+    if "plain" in res:
+        p, e = res["plain"], res["es"]
+        lo_f, _ = wilson(h["errors"], B, 1.6448536269514722)
+        _, hi_p = wilson(p["errors"], B, 1.6448536269514722)
+        line["reference_modes"] = {
+            k: {"mbps": round(v["mbps"], 2), "ms_per_step": round(v["ms"], 4),
+                "fer": v["fer"], "avg_iters": round(v["iters"], 3),
+                "pe_per_frame": round(v["pe"], 1)}
+            for k, v in (("plain40", p), ("early_stop", e))}
+        line["speedup_vs_plain40"] = round(p["ms"] / h["ms"], 3)
+        line["fer_matched"] = bool(lo_f <= hi_p)
+    if not args.no_cpu_baseline:
+        d_host = d_llr.cpu().numpy()
+        opts = dict(MODES["es_frz"], max_iter=max_iter, alpha=alpha)
+        line["cpu_baseline"] = cpu_baseline(d_host, frozen, h["info"], opts, K,
+                                            args.cpu_seconds)
+    line["input_generation_s"] = round(gen_s, 2)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,133 @@
+/*
+ * pbp.h -- C-ABI of the MI355X polar-code belief-propagation decoder.
+ *
+ * Method: Abbas, Fan, Chen, Tsui, "Low Complexity Belief Propagation Polar
+ * Code Decoder".  An (n,k) polar code carries k information bits in the
+ * reliable positions of the source word u and zeros in the n-k frozen ones;
+ * the codeword is x = u F^{(x)m}, F = [[1,0],[1,1]], n = 2^m (Section II).
+ * Decoding runs BP on the m-stage factor graph with the scaled min-sum PE
+ * update of eq. (1), optionally stopping early on the G-matrix criterion
+ * and freezing converged connected sub-factor-graphs (CSFGs, Section III,
+ * eqs. (2)-(4)).
+ *
+ * Conventions used by every call:
+ *  - N is a power of two, 2 <= N <= 16384 (the code length n); K is the
+ *    number of information bits, 0 <= K <= N.
+ *  - Bits are uint8 values 0/1.  Information bits are ordered by increasing
+ *    source-word position.  LLRs are FP32, ln P(bit=0)/P(bit=1): positive
+ *    favours 0.  Batches are row-major: frame f occupies [f*N, (f+1)*N).
+ *  - "device" pointers are HIP device memory of the current device; "host"
+ *    pointers are ordinary host memory.  The caller owns every buffer it
+ *    passes; the library owns only pbp_code handles.
+ *  - `stream` is a hipStream_t (NULL: the default stream).  Device calls are
+ *    asynchronous: they return after enqueuing, and results are valid once
+ *    the stream has been synchronised.
+ *  - Every call returns a pbp_status.  Arguments are checked on the host
+ *    before anything is enqueued; a rejected call enqueues nothing.  No
+ *    exception crosses the boundary.
+ */
+#ifndef PBP_H
+#define PBP_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    PBP_OK = 0,
+    PBP_EINVAL = -1,        /* an argument is out of range or inconsistent */
+    PBP_ENOMEM = -2,        /* a host or device allocation failed          */
+    PBP_EDEVICE = -3,       /* a HIP runtime call failed                   */
+    PBP_EUNSUPPORTED = -4   /* valid request this build does not handle    */
+} pbp_status;
+
+/* Opaque, immutable code handle: N, K, the frozen set and its device copy. */
+typedef struct pbp_code pbp_code;
+
+/* Decoder options.
+ *  max_iter      >= 1; the paper's experiments use 40 (Section IV).
+ *  early_stop    0: none (the baseline decoder always runs max_iter
+ *                iterations); 1: G-matrix criterion, checked after every
+ *                iteration: stop when uhat G equals the hard decision of the
+ *                total belief R + L at the channel column.
+ *  freezing      0/1: CSFG freezing of Section III.
+ *  freeze_input  the messages eq. (2) hard-decides: 0 = R at column j+1 as
+ *                printed; 1 = the total belief R + L at column j+1.
+ *  freeze_walk   what follows a successful freeze within one iteration:
+ *                0 = no further check this iteration; 1 = continue at the
+ *                next stage; 2 = keep checking the next CSFG of the stage.
+ *  alpha         min-sum scale of eq. (1) (0.9375 in Section IV), > 0.
+ */
+typedef struct {
+    int32_t max_iter;
+    int32_t early_stop;
+    int32_t freezing;
+    int32_t freeze_input;
+    int32_t freeze_walk;
+    float alpha;
+} pbp_decode_opts;
+
+/* Human-readable text of a status code (static storage). */
+const char *pbp_status_string(int32_t status);
+
+/* Code construction (Section II: information bits go to the K most reliable
+ * positions; the paper gives no construction method).  Positions are ranked
+ * by the Bhattacharyya parameter of the recursion z_{2i} = 2z_i - z_i^2,
+ * z_{2i+1} = z_i^2 from z_0 = exp(-(K/N) 10^(design_ebn0_db/10)), evaluated
+ * in the log domain; the N-K largest are frozen, ties freezing the lower
+ * index.  Host only.  frozen_out: host, N bytes, 1 = frozen.
+ * Errors: PBP_EINVAL for a bad N or K or a NULL pointer. */
+int32_t pbp_construct(int32_t N, int32_t K, double design_ebn0_db,
+                      uint8_t *frozen_out);
+
+/* Create a code handle from a frozen mask (host, N bytes, nonzero =
+ * frozen).  The number of frozen positions must be N-K.  Allocates device
+ * memory on the current device; the handle is then used on that device.
+ * Errors: PBP_EINVAL, PBP_ENOMEM, PBP_EDEVICE. */
+int32_t pbp_code_create(int32_t N, int32_t K, const uint8_t *frozen,
+                        pbp_code **out);
+
+/* Release a handle (NULL is ignored).  Synchronises the device first, so
+ * no enqueued call may still use it. */
+void pbp_code_destroy(pbp_code *code);
+
+/* N and K of a handle; either out pointer may be NULL. */
+int32_t pbp_code_dims(const pbp_code *code, int32_t *N, int32_t *K);
+
+/* Encoding (Section II, Fig. 1): place the K information bits of each frame
+ * at the information positions, zeros at the frozen ones, and compute
+ * x = u F^{(x)m}.
+ *   info      device, B x K uint8 (0/1)
+ *   codeword  device, B x N uint8 (0/1), written
+ * B >= 0 (0 enqueues nothing).  Errors: PBP_EINVAL, PBP_EDEVICE. */
+int32_t pbp_encode(const pbp_code *code, const uint8_t *info, int64_t B,
+                   uint8_t *codeword, void *stream);
+
+/* BP decoding of a batch (Section II-A eq. (1), Section III, Section IV).
+ * One iteration activates the PEs stage by stage from the channel column to
+ * the source-word column; stage j computes L at column j from the previous
+ * iteration's L at column j+1 and R at column j+1 from R at column j.  The
+ * initial messages are the channel LLRs for R at column 1, +inf (frozen) /
+ * 0 (information) for L at column m+1, and 0 elsewhere.
+ *   llr       device, B x N FP32 channel LLRs (finite)
+ *   opts      host, see pbp_decode_opts
+ *   info_out  device, B x K uint8, the decided information bits
+ *   iters_out device, B int32, iterations executed per frame
+ *   pe_out    device, B int64, PE activations per frame (Section IV's
+ *             computation count), or NULL
+ *   soft_out  device, B x N FP32, or NULL: the posterior LLR of each source
+ *             bit at exit (R + L at column m+1; +-inf inside frozen CSFGs)
+ * Errors: PBP_EINVAL (bad options, B < 0, NULL required pointer),
+ * PBP_EDEVICE (launch failure). */
+int32_t pbp_decode(const pbp_code *code, const float *llr, int64_t B,
+                   const pbp_decode_opts *opts, uint8_t *info_out,
+                   int32_t *iters_out, int64_t *pe_out, float *soft_out,
+                   void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PBP_H */

@@ -1,0 +1,12 @@
+"""MI355X-native belief-propagation decoding of polar codes with
+sub-factor-graph freezing (Abbas, Fan, Chen, Tsui).
+
+The decoder is hand-written HIP for gfx950 behind the C-ABI of
+include/pbp.h; this package is its Python binding (device memory and streams
+come from torch).  Build the library with ``python -m
+paper_1505_04979_amd.build``.
+"""
+
+from .binding import (Code, PbpError, exported_symbols, lib, make_opts,  # noqa
+                      pbp_code_create, pbp_code_dims, pbp_construct,
+                      pbp_decode, pbp_decode_opts, pbp_encode, status_string)

@@ -1,0 +1,207 @@
+"""Thin Python binding of libpbp (include/pbp.h): argument marshalling only.
+
+Every function here has the name of the C entry point it calls.  Device
+buffers are torch tensors on a ROCm device (torch supplies memory and
+streams, nothing else); every step of decoding runs in the HIP library.
+There is no CPU fallback: without the built library, or given host tensors
+where device memory is required, these functions raise.
+"""
+
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libpbp.so")
+
+PBP_OK = 0
+
+_P = ctypes.c_void_p
+
+
+class pbp_decode_opts(ctypes.Structure):
+    _fields_ = [("max_iter", ctypes.c_int32), ("early_stop", ctypes.c_int32),
+                ("freezing", ctypes.c_int32), ("freeze_input", ctypes.c_int32),
+                ("freeze_walk", ctypes.c_int32), ("alpha", ctypes.c_float)]
+
+
+class PbpError(RuntimeError):
+    def __init__(self, fn, status):
+        self.status = status
+        super().__init__(f"{fn} failed: {status_string(status)} ({status})")
+
+
+_lib = None
+
+# (name, restype, argtypes) of every exported entry point
+_SIGNATURES = [
+    ("pbp_status_string", ctypes.c_char_p, [ctypes.c_int32]),
+    ("pbp_construct", ctypes.c_int32,
+     [ctypes.c_int32, ctypes.c_int32, ctypes.c_double, _P]),
+    ("pbp_code_create", ctypes.c_int32,
+     [ctypes.c_int32, ctypes.c_int32, _P, ctypes.POINTER(_P)]),
+    ("pbp_code_destroy", None, [_P]),
+    ("pbp_code_dims", ctypes.c_int32, [_P, _P, _P]),
+    ("pbp_encode", ctypes.c_int32, [_P, _P, ctypes.c_int64, _P, _P]),
+    ("pbp_decode", ctypes.c_int32,
+     [_P, _P, ctypes.c_int64, ctypes.POINTER(pbp_decode_opts), _P, _P, _P, _P,
+      _P]),
+]
+
+
+def lib():
+    """Load libpbp.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(
+                f"{LIB_PATH} is missing; build it with "
+                "`python -m paper_1505_04979_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, res, args in _SIGNATURES:
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def exported_symbols():
+    return [s[0] for s in _SIGNATURES]
+
+
+def status_string(status):
+    return lib().pbp_status_string(int(status)).decode()
+
+
+def _check(fn, status):
+    if status != PBP_OK:
+        raise PbpError(fn, status)
+
+
+def _dev_ptr(t, dtype, shape, name):
+    import torch
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a device tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {shape}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    import torch
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def pbp_construct(N, K, design_ebn0_db=0.0):
+    """Frozen mask (numpy uint8, 1 = frozen) of an (N, K) code."""
+    out = np.zeros(int(N), np.uint8)
+    _check("pbp_construct", lib().pbp_construct(
+        int(N), int(K), float(design_ebn0_db), out.ctypes.data_as(_P)))
+    return out
+
+
+class Code:
+    """Owns a pbp_code handle (pbp_code_create / pbp_code_destroy)."""
+
+    def __init__(self, N, K, frozen):
+        frozen = np.ascontiguousarray(frozen, dtype=np.uint8)
+        if frozen.shape != (int(N),):
+            raise ValueError("frozen must have N entries")
+        h = _P()
+        _check("pbp_code_create", lib().pbp_code_create(
+            int(N), int(K), frozen.ctypes.data_as(_P), ctypes.byref(h)))
+        self._h = h
+        self.N, self.K = int(N), int(K)
+        self.m = self.N.bit_length() - 1
+        self.frozen = frozen.copy()
+
+    @property
+    def handle(self):
+        return self._h
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().pbp_code_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def pbp_code_create(N, K, frozen):
+    return Code(N, K, frozen)
+
+
+def pbp_code_dims(code):
+    n = ctypes.c_int32()
+    k = ctypes.c_int32()
+    _check("pbp_code_dims", lib().pbp_code_dims(code.handle, ctypes.byref(n),
+                                                ctypes.byref(k)))
+    return n.value, k.value
+
+
+def pbp_encode(code, info, codeword=None, stream=None):
+    """Codewords (B, N) uint8 of information bits ``info`` (B, K) uint8."""
+    import torch
+    B = int(info.shape[0])
+    if codeword is None:
+        codeword = torch.empty((B, code.N), dtype=torch.uint8, device=info.device)
+    _check("pbp_encode", lib().pbp_encode(
+        code.handle, _dev_ptr(info, torch.uint8, (B, code.K), "info"), B,
+        _dev_ptr(codeword, torch.uint8, (B, code.N), "codeword"),
+        _stream(stream)))
+    return codeword
+
+
+def make_opts(max_iter=40, early_stop=True, freezing=False, freeze_input=1,
+              freeze_walk=0, alpha=0.9375):
+    return pbp_decode_opts(int(max_iter), int(bool(early_stop)),
+                           int(bool(freezing)), int(freeze_input),
+                           int(freeze_walk), float(alpha))
+
+
+def pbp_decode(code, llr, opts=None, pe=True, soft=False, out=None,
+               stream=None, **kw):
+    """Decode FP32 LLRs (B, N) on the device.
+
+    Returns a dict of device tensors: ``info`` (B, K) uint8, ``iters`` (B,)
+    int32, ``pe`` (B,) int64 when asked, ``soft`` (B, N) float32 when asked.
+    ``opts`` is a pbp_decode_opts or None (then keyword options apply).
+    Pass ``out`` (a dict of preallocated tensors) to avoid allocation.
+    """
+    import torch
+    if opts is None:
+        opts = make_opts(**kw)
+    B = int(llr.shape[0])
+    dev = llr.device
+    o = dict(out or {})
+    if "info" not in o:
+        o["info"] = torch.empty((B, code.K), dtype=torch.uint8, device=dev)
+    if "iters" not in o:
+        o["iters"] = torch.empty((B,), dtype=torch.int32, device=dev)
+    if pe and "pe" not in o:
+        o["pe"] = torch.empty((B,), dtype=torch.int64, device=dev)
+    if soft and "soft" not in o:
+        o["soft"] = torch.empty((B, code.N), dtype=torch.float32, device=dev)
+    _check("pbp_decode", lib().pbp_decode(
+        code.handle, _dev_ptr(llr, torch.float32, (B, code.N), "llr"), B,
+        ctypes.byref(opts),
+        _dev_ptr(o["info"], torch.uint8, (B, code.K), "info"),
+        _dev_ptr(o["iters"], torch.int32, (B,), "iters"),
+        _dev_ptr(o.get("pe") if pe else None, torch.int64, (B,), "pe"),
+        _dev_ptr(o.get("soft") if soft else None, torch.float32, (B, code.N),
+                 "soft"),
+        _stream(stream)))
+    return o

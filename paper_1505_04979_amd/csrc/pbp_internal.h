@@ -1,0 +1,43 @@
+// Internal declarations shared by the host and kernel translation units of
+// libpbp (not part of the public ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <vector>
+
+#include "pbp.h"
+
+struct pbp_code {
+    int32_t N = 0, K = 0, m = 0;
+    int device = 0;
+    std::vector<uint8_t> frozen;       // host, N bytes
+    std::vector<int32_t> info_pos;     // host, K positions, increasing
+    uint64_t *d_frozen_words = nullptr;  // device, frozen bit mask, row i is
+                                         // bit (i & 63) of word i >> 6
+    int32_t *d_info_pos = nullptr;     // device, K entries (at least 1)
+    float *d_state = nullptr;          // device message state for codes whose
+    int64_t state_slots = 0;           // state does not fit in LDS
+    int64_t state_floats_per_slot = 0;
+};
+
+namespace pbp {
+
+inline bool valid_n(int32_t N)
+{
+    return N >= 2 && N <= 16384 && (N & (N - 1)) == 0;
+}
+
+inline int log2i(int32_t N)
+{
+    int m = 0;
+    while ((1 << m) < N)
+        m++;
+    return m;
+}
+
+// Largest code length whose full message state lives in LDS.
+constexpr int kMaxLdsLog = 11;
+
+}  // namespace pbp

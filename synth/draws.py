@@ -4,12 +4,28 @@ All functions take ``frame0`` (the first frame index) and a count ``B`` so
 that any slice of a workload can be regenerated on its own.
 """
 
+import os
+from concurrent.futures import ThreadPoolExecutor
+
 import numpy as np
 
 from .philox import (PURPOSE_BITS, PURPOSE_NOISE, PURPOSE_UNIFORM, SEED,
                      philox4x32_10, u53)
 
-_CHUNK_WORDS = 1 << 21  # Philox calls per chunk (bounds host memory)
+_CHUNK_WORDS = 1 << 20  # Philox calls per chunk (bounds host memory)
+_THREADS = max(1, min(16, os.cpu_count() or 1))
+
+
+def _run_blocks(B, words, fn):
+    """Run fn(lo, hi) over frame blocks; numpy releases the GIL inside its
+    array kernels, so the blocks proceed in parallel threads."""
+    blocks = list(_blocks(B, words))
+    if len(blocks) <= 1 or _THREADS == 1:
+        for lo, hi in blocks:
+            fn(lo, hi)
+        return
+    with ThreadPoolExecutor(_THREADS) as ex:
+        list(ex.map(lambda b: fn(*b), blocks))
 
 
 def stream_id(config, point):
@@ -41,13 +57,15 @@ def info_bits(K, B, frame0=0, seed=SEED, stream=0):
     words = (K + 127) // 128
     w = np.arange(words, dtype=np.uint64)
     shifts = np.arange(32, dtype=np.uint64)
-    for lo, hi in _blocks(B, words):
+    def blk(lo, hi):
         flo, fhi = _frames(frame0 + lo, hi - lo)
         r = philox4x32_10(w[None, :], flo[:, None], fhi[:, None],
                           PURPOSE_BITS, seed, stream)
         # (b, words, 4, 32) bits -> (b, words*128)
         bits = (np.stack(r, axis=-1)[..., None] >> shifts) & np.uint64(1)
         out[lo:hi] = bits.reshape(hi - lo, words * 128)[:, :K]
+
+    _run_blocks(B, words * 32, blk)
     return out
 
 
@@ -64,7 +82,7 @@ def normals(N, B, frame0=0, seed=SEED, stream=0):
         return out
     words = N // 2
     w = np.arange(words, dtype=np.uint64)
-    for lo, hi in _blocks(B, words):
+    def blk(lo, hi):
         flo, fhi = _frames(frame0 + lo, hi - lo)
         r0, r1, r2, r3 = philox4x32_10(w[None, :], flo[:, None], fhi[:, None],
                                        PURPOSE_NOISE, seed, stream)
@@ -72,9 +90,11 @@ def normals(N, B, frame0=0, seed=SEED, stream=0):
         u2 = u53(r2, r3)
         rad = np.sqrt(-2.0 * np.log(1.0 - u1))
         th = (2.0 * np.pi) * u2
-        blk = out[lo:hi]
-        blk[:, 0::2] = rad * np.cos(th)
-        blk[:, 1::2] = rad * np.sin(th)
+        o = out[lo:hi]
+        o[:, 0::2] = rad * np.cos(th)
+        o[:, 1::2] = rad * np.sin(th)
+
+    _run_blocks(B, words, blk)
     return out
 
 

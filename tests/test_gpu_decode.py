@@ -1,0 +1,193 @@
+"""GPU parity of the HIP path against the FP32 oracle, through the C-ABI.
+
+Bar: information bits, iteration counts and PE counts bit-exact; posterior
+(soft) outputs equal as FP32 values (the same operation order gives the
+same bits; -0 and +0 compare equal); error rates of the GPU inside the FP64
+oracle's 95% interval.
+"""
+
+import numpy as np
+import pytest
+
+import oracle
+from helpers import frozen_mask, make_frames, noiseless_llr, wilson
+
+pytestmark = pytest.mark.gpu
+
+MODES = {
+    "plain": dict(early_stop=False, freezing=False),
+    "es": dict(early_stop=True, freezing=False),
+    "es_frz_total": dict(early_stop=True, freezing=True, freeze_input=1),
+    "es_frz_r": dict(early_stop=True, freezing=True, freeze_input=0),
+    "frz_total": dict(early_stop=False, freezing=True, freeze_input=1),
+    "es_frz_stage": dict(early_stop=True, freezing=True, freeze_walk=1),
+    "es_frz_greedy": dict(early_stop=True, freezing=True, freeze_walk=2),
+}
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1505_04979_amd as pbp
+    pbp.lib()
+    return pbp, torch
+
+
+_codes = {}
+
+
+def code_of(pbp, N, K):
+    if (N, K) not in _codes:
+        _codes[(N, K)] = pbp.Code(N, K, frozen_mask(N, K))
+    return _codes[(N, K)]
+
+
+def gpu_decode(env, N, K, llr, max_iter=40, alpha=0.9375, **mode):
+    pbp, torch = env
+    code = code_of(pbp, N, K)
+    d = torch.from_numpy(llr).cuda()
+    o = pbp.pbp_decode(code, d, max_iter=max_iter, alpha=alpha, soft=True,
+                       **mode)
+    torch.cuda.synchronize()
+    return {k: v.cpu().numpy() for k, v in o.items()}
+
+
+def assert_parity(g, r, K, frozen):
+    assert np.array_equal(g["info"], r["uhat"][:, frozen == 0])
+    assert np.array_equal(g["iters"], r["iters"])
+    assert np.array_equal(g["pe"], r["pe"])
+    gs, rs = g["soft"], r["soft"]
+    same = (gs == rs) | (np.isnan(gs) & np.isnan(rs))
+    assert same.all(), np.argwhere(~same)[:5]
+
+
+CASES = [
+    # N, K, Eb/N0, frames
+    (2, 1, 1.0, 64),
+    (8, 4, 2.0, 200),
+    (64, 32, 2.5, 400),
+    (128, 64, 2.0, 200),
+    (256, 85, 2.0, 100),
+    (1024, 512, 3.0, 160),
+    (1024, 512, 1.5, 64),
+    (2048, 1024, 2.5, 16),
+    (4096, 2048, 2.5, 12),
+    (16384, 8192, 2.0, 3),
+]
+
+
+@pytest.mark.parametrize("N,K,ebn0,B", CASES)
+@pytest.mark.parametrize("mode", list(MODES))
+def test_decode_parity(env, N, K, ebn0, B, mode):
+    print(f"[parity] N={N} K={K} ebn0={ebn0} B={B} mode={mode}", flush=True)
+    fz = frozen_mask(N, K)
+    u, x, llr = make_frames(N, K, B, ebn0, stream=1000 + N)
+    kw = MODES[mode]
+    mi = 60 if N >= 4096 else 40
+    r = oracle.decode(llr, fz, max_iter=mi, soft=True, **kw)
+    g = gpu_decode(env, N, K, llr, max_iter=mi, **kw)
+    assert_parity(g, r, K, fz)
+
+
+@pytest.mark.parametrize("N,K", [(16, 0), (16, 16), (64, 1), (64, 63)])
+@pytest.mark.parametrize("mode", ["plain", "es", "es_frz_total", "es_frz_greedy"])
+def test_degenerate_rates(env, N, K, mode):
+    fz = frozen_mask(N, K)
+    u, x, llr = make_frames(N, K, 50, 1.0, stream=77)
+    r = oracle.decode(llr, fz, soft=True, **MODES[mode])
+    g = gpu_decode(env, N, K, llr, **MODES[mode])
+    assert_parity(g, r, K, fz)
+
+
+@pytest.mark.parametrize("max_iter,alpha", [(1, 0.9375), (3, 1.0), (17, 0.5),
+                                            (40, 0.8125)])
+def test_options(env, max_iter, alpha):
+    N, K = 256, 128
+    fz = frozen_mask(N, K)
+    u, x, llr = make_frames(N, K, 64, 2.0, stream=78)
+    for mode in ("plain", "es_frz_total"):
+        r = oracle.decode(llr, fz, max_iter=max_iter, alpha=alpha, soft=True,
+                          **MODES[mode])
+        g = gpu_decode(env, N, K, llr, max_iter=max_iter, alpha=alpha,
+                       **MODES[mode])
+        assert_parity(g, r, K, fz)
+
+
+@pytest.mark.parametrize("N", [64, 1024, 16384])
+def test_noiseless_closed_forms(env, N):
+    K = N // 2
+    u, x, _ = make_frames(N, K, 4, 3.0, stream=79)
+    llr = noiseless_llr(x)
+    m = N.bit_length() - 1
+    g = gpu_decode(env, N, K, llr, **MODES["es_frz_total"])
+    assert np.array_equal(g["info"], u[:, frozen_mask(N, K) == 0])
+    assert np.all(g["iters"] == 1)
+    assert np.all(g["pe"] == N // 2 + (m - 1) * N // 4)
+    g = gpu_decode(env, N, K, llr, **MODES["plain"])
+    assert np.all(g["pe"] == 40 * m * N // 2)
+
+
+def test_encode_parity(env):
+    pbp, torch = env
+    for N, K in ((2, 1), (8, 4), (64, 32), (1024, 512), (4096, 1365),
+                 (16384, 8192), (32, 0), (32, 32)):
+        code = code_of(pbp, N, K)
+        fz = frozen_mask(N, K)
+        rng = np.random.default_rng(N + K)
+        info = rng.integers(0, 2, size=(37, K)).astype(np.uint8)
+        u = np.zeros((37, N), np.uint8)
+        u[:, fz == 0] = info
+        cw = pbp.pbp_encode(code, torch.from_numpy(info).cuda())
+        torch.cuda.synchronize()
+        assert np.array_equal(cw.cpu().numpy(), oracle.encode(u))
+
+
+def test_large_batch_sampled_parity(env):
+    """The benchmark's launch shape (2^16 frames of the (1024, 512) code at
+    3 dB, early stop + freezing), checked on sampled frames."""
+    pbp, torch = env
+    N, K, B = 1024, 512, 1 << 16
+    fz = frozen_mask(N, K)
+    u, x, llr = make_frames(N, K, B, 3.0, stream=2024)
+    g = gpu_decode(env, N, K, llr, **MODES["es_frz_total"])
+    idx = np.random.default_rng(0).choice(B, 96, replace=False)
+    r = oracle.decode(llr[idx], fz, soft=True, **MODES["es_frz_total"])
+    sub = {k: v[idx] for k, v in g.items()}
+    assert_parity(sub, r, K, fz)
+    # error rate within the FP64 oracle's interval on a subsample
+    sidx = idx[:96]
+    r64 = oracle.decode(llr[sidx], fz, prec="f64", **MODES["es_frz_total"])
+    e64 = int(np.sum(np.any(r64["uhat"] != u[sidx], axis=1)))
+    lo, hi = wilson(e64, len(sidx))
+    eg = float(np.mean(np.any(g["info"][sidx] != u[sidx][:, fz == 0], axis=1)))
+    assert lo - 0.02 <= eg <= hi + 0.02
+
+
+def test_repeatable(env):
+    N, K = 1024, 512
+    u, x, llr = make_frames(N, K, 256, 2.5, stream=81)
+    a = gpu_decode(env, N, K, llr, **MODES["es_frz_total"])
+    b = gpu_decode(env, N, K, llr, **MODES["es_frz_total"])
+    for k in a:
+        assert np.array_equal(a[k], b[k])
+
+
+def test_rejects_bad_arguments(env):
+    pbp, torch = env
+    code = code_of(pbp, 64, 32)
+    llr = torch.zeros((4, 64), dtype=torch.float32, device="cuda")
+    for bad in (dict(max_iter=0), dict(freeze_input=2), dict(freeze_walk=3),
+                dict(alpha=0.0), dict(alpha=float("inf"))):
+        with pytest.raises(pbp.PbpError):
+            pbp.pbp_decode(code, llr, **bad)
+    with pytest.raises(TypeError):
+        pbp.pbp_decode(code, llr.cpu())
+    with pytest.raises(ValueError):
+        pbp.pbp_decode(code, torch.zeros((4, 32), dtype=torch.float32,
+                                         device="cuda"))
+    # an empty batch enqueues nothing
+    o = pbp.pbp_decode(code, torch.zeros((0, 64), dtype=torch.float32,
+                                         device="cuda"))
+    assert o["info"].shape == (0, 32)
