@@ -243,10 +243,17 @@ __global__ void bp_decode_kernel(DecodeParams P)
                         for (int q = 0; q < kMaxWordsPerLane; q++) {
                             const int w = lane + 64 * q;
                             if (w < nw) {
-                                if (h >= 64)
+                                // a CSFG may cover sub-CSFGs of later
+                                // stages frozen before it: its decisions
+                                // replace theirs
+                                if (h >= 64) {
                                     dw[(r0 >> 6) + w] = r[q];
-                                else
-                                    dw[r0 >> 6] |= r[q] << (r0 & 63);
+                                } else {
+                                    const uint64_t msk = ((1ull << h) - 1)
+                                                         << (r0 & 63);
+                                    dw[r0 >> 6] = (dw[r0 >> 6] & ~msk) |
+                                                  (r[q] << (r0 & 63));
+                                }
                             }
                         }
                         for (int i = lane; i < h; i += 64) {

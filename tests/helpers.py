@@ -24,7 +24,8 @@ def make_frames(N, K, B, ebn0_db, stream, frame0=0, frozen=None):
     u[:, frozen == 0] = synth.info_bits(K, B, frame0=frame0, stream=stream)
     x = oracle.encode(u)
     nz = synth.normals(N, B, frame0=frame0, stream=stream)
-    llr = synth.channel_llr(x, nz, ebn0_db, K / N)
+    # a rate-0 code has no Eb; its channel is set as if it carried one bit
+    llr = synth.channel_llr(x, nz, ebn0_db, max(K, 1) / N)
     return u, x, llr
 
 
