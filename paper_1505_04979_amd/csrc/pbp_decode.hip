@@ -12,6 +12,7 @@
 #include <hip/hip_runtime.h>
 
 #include "pbp_internal.h"
+#include "pbp_r10.h"
 
 namespace {
 
@@ -474,6 +475,15 @@ extern "C" int32_t pbp_decode(const pbp_code *code, const float *llr, int64_t B,
     P.soft_out = soft_out;
     hipStream_t st = (hipStream_t)stream;
     hipError_t e;
+    // the register-resident N = 1024 kernel moves LLRs and posteriors as
+    // 16-byte vectors
+    const bool aligned16 = !(reinterpret_cast<uintptr_t>(llr) & 15) &&
+                           !(reinterpret_cast<uintptr_t>(soft_out) & 15);
+    if (code->m == pbp::r10::M && code->d_fzw10 && aligned16) {
+        e = pbp::r10::launch(code, llr, B, opts, info_out, iters_out, pe_out,
+                             soft_out, st);
+        return e == hipSuccess ? PBP_OK : PBP_EDEVICE;
+    }
     switch (code->m) {
     case 1: e = launch_decode<1>(code, P, st); break;
     case 2: e = launch_decode<2>(code, P, st); break;

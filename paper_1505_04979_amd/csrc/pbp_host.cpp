@@ -8,6 +8,7 @@
 #include <vector>
 
 #include "pbp_internal.h"
+#include "pbp_r10.h"
 
 extern "C" const char *pbp_status_string(int32_t status)
 {
@@ -79,6 +80,10 @@ void free_code(pbp_code *c)
         (void)hipFree(c->d_info_pos);
     if (c->d_state)
         (void)hipFree(c->d_state);
+    if (c->d_counter)
+        (void)hipFree(c->d_counter);
+    if (c->d_fzw10)
+        (void)hipFree(c->d_fzw10);
     delete c;
 }
 
@@ -139,16 +144,32 @@ extern "C" int32_t pbp_code_create(int32_t N, int32_t K, const uint8_t *frozen,
         free_code(c);
         return PBP_EDEVICE;
     }
-    if (c->m > pbp::kMaxLdsLog) {
-        // message state of codes too long for LDS: one slot per resident
-        // workgroup, (m + 1) columns of N floats each
-        int cus = 0;
-        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount,
-                                  c->device) != hipSuccess) {
+    if (hipDeviceGetAttribute(&c->cus, hipDeviceAttributeMultiprocessorCount,
+                              c->device) != hipSuccess) {
+        free_code(c);
+        return PBP_EDEVICE;
+    }
+    if (hipMalloc(&c->d_counter, sizeof(int)) != hipSuccess) {
+        free_code(c);
+        return PBP_ENOMEM;
+    }
+    if (c->m == pbp::r10::M) {
+        uint64_t fzw[4 * pbp::r10::Q];
+        pbp::r10::frozen_words(c->frozen.data(), fzw);
+        if (hipMalloc(&c->d_fzw10, sizeof(fzw)) != hipSuccess) {
+            free_code(c);
+            return PBP_ENOMEM;
+        }
+        if (hipMemcpy(c->d_fzw10, fzw, sizeof(fzw), hipMemcpyHostToDevice) !=
+            hipSuccess) {
             free_code(c);
             return PBP_EDEVICE;
         }
-        c->state_slots = (int64_t)cus * 2;
+    }
+    if (c->m > pbp::kMaxLdsLog) {
+        // message state of codes too long for LDS: one slot per resident
+        // workgroup, (m + 1) columns of N floats each
+        c->state_slots = (int64_t)c->cus * 2;
         c->state_floats_per_slot = (int64_t)(c->m + 1) * N;
         if (hipMalloc(&c->d_state, sizeof(float) * c->state_slots *
                                        c->state_floats_per_slot) != hipSuccess) {

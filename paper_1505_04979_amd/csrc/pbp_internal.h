@@ -20,6 +20,9 @@ struct pbp_code {
     float *d_state = nullptr;          // device message state for codes whose
     int64_t state_slots = 0;           // state does not fit in LDS
     int64_t state_floats_per_slot = 0;
+    int cus = 0;                       // compute units of the device
+    int *d_counter = nullptr;          // frame counter of persistent kernels
+    uint64_t *d_fzw10 = nullptr;       // N = 1024: frozen ballot words [4][16]
 };
 
 namespace pbp {

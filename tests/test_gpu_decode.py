@@ -191,3 +191,23 @@ def test_rejects_bad_arguments(env):
     o = pbp.pbp_decode(code, torch.zeros((0, 64), dtype=torch.float32,
                                          device="cuda"))
     assert o["info"].shape == (0, 32)
+
+
+def test_unaligned_buffers_take_the_generic_kernel(env):
+    """N = 1024 LLRs at an address that is not 16-byte aligned are decoded by
+    the generic kernel, with the same results."""
+    pbp, torch = env
+    N, K = 1024, 512
+    fz = frozen_mask(N, K)
+    u, x, llr = make_frames(N, K, 40, 2.5, stream=83)
+    code = code_of(pbp, N, K)
+    buf = torch.zeros(40 * N + 1, dtype=torch.float32, device="cuda")
+    view = buf[1:].view(40, N)
+    view.copy_(torch.from_numpy(llr))
+    assert view.data_ptr() % 16 != 0
+    kw = MODES["es_frz_total"]
+    o = pbp.pbp_decode(code, view, soft=True, **kw)
+    torch.cuda.synchronize()
+    g = {k: v.cpu().numpy() for k, v in o.items()}
+    r = oracle.decode(llr, fz, soft=True, **kw)
+    assert_parity(g, r, K, fz)
