@@ -19,14 +19,15 @@ namespace {
 constexpr float kInf = __builtin_inff();
 
 // The min-sum term of eq. (1): alpha * sign(x) * sign(y) * min(|x|, |y|).
-// The magnitude alpha * min(|x|,|y|) rounds once; its sign is the XOR of
-// the operands' sign bits (which differs from the product of signs only in
-// the sign of a zero result, invisible to every value and decision).
+// A zero result may carry either sign; no value or decision depends on it.
 __device__ __forceinline__ float gmin(float x, float y, float alpha)
 {
-    const float mag = alpha * fminf(fabsf(x), fabsf(y));
-    const uint32_t sgn = (__float_as_uint(x) ^ __float_as_uint(y)) & 0x80000000u;
-    return __uint_as_float(__float_as_uint(mag) | sgn);
+    // sign(x) sign(y) min(|x|, |y|) is y, its sign flipped when x < 0,
+    // clamped to [-|x|, |x|]: one median of three (exact, a selection); the
+    // product with alpha then rounds once, symmetrically in sign
+    const float t = __uint_as_float(__float_as_uint(y) ^
+                                    (__float_as_uint(x) & 0x80000000u));
+    return alpha * __builtin_amdgcn_fmed3f(-fabsf(x), t, fabsf(x));
 }
 
 // x F^{(x)6} over the 64 bits of a word (bit i = position i): at each level

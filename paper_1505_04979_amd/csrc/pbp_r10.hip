@@ -37,9 +37,12 @@ constexpr float kInf = __builtin_inff();
 
 __device__ __forceinline__ float gmin(float x, float y, float alpha)
 {
-    const float mag = alpha * fminf(fabsf(x), fabsf(y));
-    const uint32_t sgn = (__float_as_uint(x) ^ __float_as_uint(y)) & 0x80000000u;
-    return __uint_as_float(__float_as_uint(mag) | sgn);
+    // sign(x) sign(y) min(|x|, |y|) is y, its sign flipped when x < 0,
+    // clamped to [-|x|, |x|]: one median of three (exact, a selection); the
+    // product with alpha then rounds once, symmetrically in sign
+    const float t = __uint_as_float(__float_as_uint(y) ^
+                                    (__float_as_uint(x) & 0x80000000u));
+    return alpha * __builtin_amdgcn_fmed3f(-fabsf(x), t, fabsf(x));
 }
 
 __device__ __forceinline__ void wave_sync()
