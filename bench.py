@@ -33,6 +33,11 @@ METRIC = ("decoded info Mbit/s at N=1024 R=1/2 3.0dB, FER-matched; "
 VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
 OPS_PER_PE = 12
 
+# the kernel one step launches (one launch per step)
+KERNEL = "bp_decode_r10_kernel<true, true>"
+KERNEL_SRC = os.path.join(ROOT, "paper_1505_04979_amd", "csrc", "pbp_r10.hip")
+TRAFFIC = os.path.join(ROOT, "profiles", "traffic_bp_decode_r10_n1024_3db.txt")
+
 MODES = {
     "es_frz": dict(early_stop=True, freezing=True, freeze_input=1, freeze_walk=0),
     "es": dict(early_stop=True, freezing=False),
@@ -79,6 +84,47 @@ def time_mode(pbp, torch, code, d_llr, opts, steps, warmup):
     wall = time.perf_counter() - t0
     ms = ev0.elapsed_time(ev1) / steps
     return ms, wall, {k: v.cpu().numpy() for k, v in out.items()}
+
+
+def source_digest():
+    import hashlib
+    with open(KERNEL_SRC, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM bytes per launch of the timed kernel from the FETCH_SIZE and
+    WRITE_SIZE counter runs recorded in the profile summary, scaled by what
+    the same counters read for a plain copy of known size; None when the
+    kernel source has changed since the counters were taken."""
+    vals = {}
+    try:
+        with open(TRAFFIC) as f:
+            for ln in f:
+                if ln.startswith("@") and "=" in ln:
+                    k, v = ln[1:].split("=", 1)
+                    vals[k.strip()] = v.strip()
+    except OSError:
+        return None
+    if vals.get("source_sha256_16") != source_digest():
+        return None
+    try:
+        return float(vals["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def copy_calibration(torch, nbytes, reps):
+    """A plain device-to-device copy of nbytes, reps times: the yardstick for
+    the HBM byte counters (reads nbytes, writes nbytes per launch)."""
+    a = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda").fill_(1.0)
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    for _ in range(reps):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_read": nbytes, "copy_bytes_written": nbytes,
+                      "launches": reps}), flush=True)
 
 
 def cpu_baseline(llr, frozen, info_ref, opts, K, seconds):
@@ -130,6 +176,9 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-reference-modes", action="store_true")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
+                    help="only run a plain device copy of BYTES (counter "
+                         "yardstick) and exit")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported "
@@ -140,6 +189,9 @@ def main():
     import torch
     import paper_1505_04979_amd as pbp
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.copy_calibration:
+        copy_calibration(torch, args.copy_calibration, max(1, args.steps))
+        return
 
     N, K, B, max_iter, alpha = 1024, 512, args.batch, 40, 0.9375
     frozen = pbp.pbp_construct(N, K, 0.0)
@@ -190,8 +242,8 @@ def main():
     line["roofline"] = {"bound": "alu", "achieved": round(achieved, 3),
                         "peak": round(VALU_PEAK_TOPS, 3), "unit": "TOP/s",
                         "frac": round(achieved / VALU_PEAK_TOPS, 4),
-                        "traffic": None,
-                        "kernel": "bp_decode_kernel<10>",
+                        "traffic": measured_traffic(),
+                        "kernel": KERNEL,
                         "kernel_ms": round(h["ms"], 4)}
     if "plain" in res:
         p, e = res["plain"], res["es"]

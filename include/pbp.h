@@ -119,6 +119,9 @@ int32_t pbp_encode(const pbp_code *code, const uint8_t *info, int64_t B,
  *             computation count), or NULL
  *   soft_out  device, B x N FP32, or NULL: the posterior LLR of each source
  *             bit at exit (R + L at column m+1; +-inf inside frozen CSFGs)
+ * A handle holds per-call device state (the frame counter of the persistent
+ * kernels, the message state of codes longer than 2048): calls on one handle
+ * must be ordered on one stream, never in flight on two streams at once.
  * Errors: PBP_EINVAL (bad options, B < 0, NULL required pointer),
  * PBP_EDEVICE (launch failure). */
 int32_t pbp_decode(const pbp_code *code, const float *llr, int64_t B,

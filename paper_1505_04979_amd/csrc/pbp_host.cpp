@@ -149,9 +149,15 @@ extern "C" int32_t pbp_code_create(int32_t N, int32_t K, const uint8_t *frozen,
         free_code(c);
         return PBP_EDEVICE;
     }
-    if (hipMalloc(&c->d_counter, sizeof(int)) != hipSuccess) {
+    // frame counter and exit counter of the persistent kernels: zero here,
+    // and rewound to zero by the last wave of each launch
+    if (hipMalloc(&c->d_counter, 2 * sizeof(int)) != hipSuccess) {
         free_code(c);
         return PBP_ENOMEM;
+    }
+    if (hipMemset(c->d_counter, 0, 2 * sizeof(int)) != hipSuccess) {
+        free_code(c);
+        return PBP_EDEVICE;
     }
     if (c->m == pbp::r10::M) {
         uint64_t fzw[4 * pbp::r10::Q];

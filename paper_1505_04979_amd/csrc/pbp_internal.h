@@ -21,7 +21,8 @@ struct pbp_code {
     int64_t state_slots = 0;           // state does not fit in LDS
     int64_t state_floats_per_slot = 0;
     int cus = 0;                       // compute units of the device
-    int *d_counter = nullptr;          // frame counter of persistent kernels
+    int *d_counter = nullptr;          // [frame, exit] counters of persistent
+                                       // kernels, zero between launches
     uint64_t *d_fzw10 = nullptr;       // N = 1024: frozen ballot words [4][16]
 };
 

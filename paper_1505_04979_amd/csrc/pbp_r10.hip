@@ -721,11 +721,12 @@ __global__ __launch_bounds__(64, 2) void bp_decode_r10_kernel(Params P)
             break;
         D.decode(frame);
     }
-}
-
-__global__ void reset_counter_kernel(int *c)
-{
-    *c = 0;
+    // every wave has taken its last frame number before it counts itself out;
+    // the last one out rewinds both counters for the next launch on the stream
+    if (lane == 0 && atomicAdd(P.counter + 1, 1) == (int)gridDim.x - 1) {
+        atomicExch(P.counter, 0);
+        atomicExch(P.counter + 1, 0);
+    }
 }
 
 }  // namespace
@@ -753,7 +754,6 @@ hipError_t launch(const pbp_code *c, const float *llr, int64_t B,
     P.iters_out = iters_out;
     P.pe_out = pe_out;
     P.soft_out = soft_out;
-    hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(1), 0, st, c->d_counter);
     int64_t grid = (int64_t)c->cus * 8;
     if (grid > B)
         grid = B;
