@@ -129,6 +129,50 @@ int32_t pbp_decode(const pbp_code *code, const float *llr, int64_t B,
                    int32_t *iters_out, int64_t *pe_out, float *soft_out,
                    void *stream);
 
+/* Unrolled BP with trainable scales (the decoder of eq. (1) unrolled over T
+ * iterations, single sweep, no early stop and no freezing), for learning the
+ * min-sum scale per iteration, stage and direction.  Iteration t, stage j:
+ *   L^t_{a,j}   = aL g(L_a, L_b + R_b),   L^t_{b,j}   = L_b + aL g(L_a, R_a),
+ *   R^t_{a,j+1} = aR g(R_a, L_b + R_b),   R^t_{b,j+1} = R_b + aR g(L_a, R_a),
+ * g(x,y) = sign(x) sign(y) min(|x|,|y|), L = L^{t-1} at column j+1,
+ * aL = alpha[t][j][0], aR = alpha[t][j][1].  With every scale equal this is
+ * pbp_decode's iteration without early stop or freezing.  N <= 1024
+ * (PBP_EUNSUPPORTED above).
+ *   llr    device, B x N FP32 channel LLRs (finite)
+ *   T      iterations, 1 <= T <= 65536
+ *   alpha  device, T x m x 2 FP32 scales (finite and nonzero)
+ *   out    device, B x N FP32, written: R^T at column m+1 (the posterior
+ *          LLR of each source bit, without the prior)
+ *   ckpt   device, T x B x (m-1) x N FP32, or NULL (inference): written with
+ *          L at columns 2..m at the start of each iteration, for the
+ *          backward pass.  Unused when N = 2.
+ * Errors: PBP_EINVAL (B < 0, T out of range, NULL required pointer),
+ * PBP_EUNSUPPORTED (N > 1024), PBP_EDEVICE. */
+int32_t pbp_unrolled_forward(const pbp_code *code, const float *llr, int64_t B,
+                             int32_t T, const float *alpha, float *out,
+                             float *ckpt, void *stream);
+
+/* Adjoint of pbp_unrolled_forward: gradients of sum(dout * out) with respect
+ * to the scales and the channel LLRs.  d g(x,y)/dx = sign(y) when
+ * |x| <= |y| (ties to x) and d g/dy = sign(x) otherwise; infinite messages
+ * (the frozen prior and what it produces) are constants and take no
+ * gradient.
+ *   llr, alpha, T  as given to the forward call
+ *   ckpt           device, the forward call's checkpoints (NULL if N = 2)
+ *   dout           device, B x N FP32, the gradient at the output
+ *   dalpha_frame   device, B x T x m x 2 FP32, written: each frame's
+ *                  contribution to the scale gradient (workspace owned by
+ *                  the caller; may be NULL only when B = 0)
+ *   dalpha         device, T x m x 2 FP32, written: the sum over frames,
+ *                  accumulated in FP64 in frame order (deterministic)
+ *   dllr           device, B x N FP32, or NULL: gradient at the channel LLRs
+ * Errors: as pbp_unrolled_forward. */
+int32_t pbp_unrolled_backward(const pbp_code *code, const float *llr,
+                              int64_t B, int32_t T, const float *alpha,
+                              const float *ckpt, const float *dout,
+                              float *dalpha_frame, float *dalpha, float *dllr,
+                              void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -9,4 +9,7 @@ paper_1505_04979_amd.build``.
 
 from .binding import (Code, PbpError, exported_symbols, lib, make_opts,  # noqa
                       pbp_code_create, pbp_code_dims, pbp_construct,
-                      pbp_decode, pbp_decode_opts, pbp_encode, status_string)
+                      pbp_decode, pbp_decode_opts, pbp_encode,
+                      pbp_unrolled_backward, pbp_unrolled_forward,
+                      status_string)
+from .unrolled import UnrolledBP, info_bce, unrolled_bp  # noqa

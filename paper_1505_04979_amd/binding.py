@@ -47,6 +47,10 @@ _SIGNATURES = [
     ("pbp_decode", ctypes.c_int32,
      [_P, _P, ctypes.c_int64, ctypes.POINTER(pbp_decode_opts), _P, _P, _P, _P,
       _P]),
+    ("pbp_unrolled_forward", ctypes.c_int32,
+     [_P, _P, ctypes.c_int64, ctypes.c_int32, _P, _P, _P, _P]),
+    ("pbp_unrolled_backward", ctypes.c_int32,
+     [_P, _P, ctypes.c_int64, ctypes.c_int32, _P, _P, _P, _P, _P, _P, _P]),
 ]
 
 
@@ -205,3 +209,58 @@ def pbp_decode(code, llr, opts=None, pe=True, soft=False, out=None,
                  "soft"),
         _stream(stream)))
     return o
+
+
+def pbp_unrolled_forward(code, llr, alpha, ckpt=True, out=None, stream=None):
+    """Unrolled BP with scales ``alpha`` (T, m, 2) float32 on the device.
+
+    Returns ``(out, ckpt)``: R^T at column m+1, (B, N) float32, and the
+    per-iteration L checkpoints (T, B, m-1, N) float32 for the backward call
+    (``ckpt=False``: none are written and None is returned; a tensor: it is
+    filled).
+    """
+    import torch
+    B, T = int(llr.shape[0]), int(alpha.shape[0])
+    m, N, dev = code.m, code.N, llr.device
+    if out is None:
+        out = torch.empty((B, N), dtype=torch.float32, device=dev)
+    if ckpt is True:
+        ckpt = torch.empty((T, B, max(m - 1, 0), N), dtype=torch.float32,
+                           device=dev)
+    elif ckpt is False:
+        ckpt = None
+    _check("pbp_unrolled_forward", lib().pbp_unrolled_forward(
+        code.handle, _dev_ptr(llr, torch.float32, (B, N), "llr"), B, T,
+        _dev_ptr(alpha, torch.float32, (T, m, 2), "alpha"),
+        _dev_ptr(out, torch.float32, (B, N), "out"),
+        _dev_ptr(ckpt, torch.float32, (T, B, max(m - 1, 0), N), "ckpt"),
+        _stream(stream)))
+    return out, ckpt
+
+
+def pbp_unrolled_backward(code, llr, alpha, ckpt, dout, dllr=True,
+                          stream=None):
+    """Gradients of sum(dout * out) of pbp_unrolled_forward.
+
+    Returns ``(dalpha, dllr, dalpha_frame)``: (T, m, 2), (B, N) or None,
+    and each frame's share of dalpha, (B, T, m, 2); all float32.
+    """
+    import torch
+    B, T = int(llr.shape[0]), int(alpha.shape[0])
+    m, N, dev = code.m, code.N, llr.device
+    dalpha = torch.empty((T, m, 2), dtype=torch.float32, device=dev)
+    dframe = torch.empty((B, T, m, 2), dtype=torch.float32, device=dev)
+    if dllr is True:
+        dllr = torch.empty((B, N), dtype=torch.float32, device=dev)
+    elif dllr is False:
+        dllr = None
+    _check("pbp_unrolled_backward", lib().pbp_unrolled_backward(
+        code.handle, _dev_ptr(llr, torch.float32, (B, N), "llr"), B, T,
+        _dev_ptr(alpha, torch.float32, (T, m, 2), "alpha"),
+        _dev_ptr(ckpt, torch.float32, (T, B, max(m - 1, 0), N), "ckpt"),
+        _dev_ptr(dout, torch.float32, (B, N), "dout"),
+        _dev_ptr(dframe, torch.float32, (B, T, m, 2), "dalpha_frame"),
+        _dev_ptr(dalpha, torch.float32, (T, m, 2), "dalpha"),
+        _dev_ptr(dllr, torch.float32, (B, N), "dllr"),
+        _stream(stream)))
+    return dalpha, dllr, dframe

@@ -22,7 +22,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libpbp.so")
-SOURCES = ["pbp_host.cpp", "pbp_decode.hip", "pbp_r10.hip"]
+SOURCES = ["pbp_host.cpp", "pbp_decode.hip", "pbp_r10.hip", "pbp_unrolled.hip"]
 
 HIPCC = os.environ.get("HIPCC", shutil.which("hipcc") or "/opt/rocm/bin/hipcc")
 ARCH = os.environ.get("PBP_OFFLOAD_ARCH", "gfx950")

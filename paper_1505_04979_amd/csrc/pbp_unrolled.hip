@@ -1,0 +1,461 @@
+// Unrolled BP with trainable scales, and its adjoint.
+//
+// T single left-to-right sweeps of eq. (1) with no early stop and no
+// freezing; the scale of stage j in iteration t is split by direction:
+//   L^t_{a,j}   = aL g(L_a, L_b + R_b)     L^t_{b,j}   = L_b + aL g(L_a, R_a)
+//   R^t_{a,j+1} = aR g(R_a, L_b + R_b)     R^t_{b,j+1} = R_b + aR g(L_a, R_a)
+// with g(x, y) = sign(x) sign(y) min(|x|, |y|) and L = L^{t-1} at column j+1
+// (Section II-A, eq. (1); with every scale equal to alpha this is plain
+// T-iteration BP).  The output is R^T at column m+1.
+//
+// One workgroup owns one frame at a time (grid-stride over frames), one
+// thread per PE of a stage, the message columns in LDS.  The forward writes
+// the L state at the start of every iteration (columns 2..m) to a caller
+// buffer; the backward reloads it, recomputes that iteration's R sweep, and
+// runs the stages in reverse with the adjoints in LDS.  Scale gradients are
+// reduced per frame in a fixed order, then over frames in FP64, so results
+// do not depend on scheduling.
+//
+// Derivatives: d g(x,y)/dx = sign(y) when |x| <= |y| (ties go to x), else
+// 0; d g(x,y)/dy = sign(x) when |x| > |y|, else 0; d(a g)/da = g.  An
+// infinite message (the frozen prior and what it produces) is a constant: it
+// takes no adjoint and adds nothing to the scale gradients.
+
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+#include "pbp.h"
+#include "pbp_internal.h"
+
+namespace {
+
+constexpr float kInf = __builtin_inff();
+
+// g(x, y) exactly: y with the sign of x folded in, clamped to [-|x|, |x|]
+__device__ __forceinline__ float g0(float x, float y)
+{
+    const float t = __uint_as_float(__float_as_uint(y) ^
+                                    (__float_as_uint(x) & 0x80000000u));
+    return __builtin_amdgcn_fmed3f(-fabsf(x), t, fabsf(x));
+}
+
+__device__ __forceinline__ bool finite(float v) { return fabsf(v) < kInf; }
+
+__device__ __forceinline__ float sgn(float v)
+{
+    return (float)((v > 0.0f) - (v < 0.0f));
+}
+
+// adjoint d of g(x, y) routed to x or y; an infinite operand takes nothing
+// (selects, not branches, so that both accumulators stay in registers)
+__device__ __forceinline__ void g0_back(float x, float y, float d, float &dx,
+                                        float &dy)
+{
+    const bool to_x = fabsf(x) <= fabsf(y);
+    const float cx = to_x && finite(x) ? d * sgn(y) : 0.0f;
+    const float cy = !to_x && finite(y) ? d * sgn(x) : 0.0f;
+    dx += cx;
+    dy += cy;
+}
+
+__device__ __forceinline__ bool frozen_at(const uint64_t *fw, int i)
+{
+    return (fw[i >> 6] >> (i & 63)) & 1;
+}
+
+template <int M>
+struct Shape {
+    static constexpr int N = 1 << M;
+    static constexpr int H = N / 2;                 // PEs per stage
+    static constexpr int NT = H < 64 ? 64 : H;      // threads per workgroup
+    static constexpr int NW = NT / 64;              // wavefronts
+};
+
+struct FwdParams {
+    const float *llr;
+    int64_t B;
+    int T;
+    const float *alpha;       // T x m x 2
+    const uint64_t *frozen;   // frozen bit words
+    float *out;               // B x N
+    float *ckpt;              // T x B x (m-1) x N, or null
+};
+
+struct BwdParams {
+    const float *llr;
+    int64_t B;
+    int T;
+    const float *alpha;
+    const uint64_t *frozen;
+    const float *ckpt;
+    const float *dout;        // B x N
+    float *dalpha_frame;      // B x T x m x 2
+    float *dllr;              // B x N, or null
+};
+
+template <int M>
+size_t fwd_lds_bytes()
+{
+    return sizeof(float) * (size_t)(M + 2) * Shape<M>::N;
+}
+
+template <int M>
+size_t bwd_lds_bytes()
+{
+    using S = Shape<M>;
+    return sizeof(float) * ((size_t)(M + M + 1 + (M - 1) + 2 + 1) * S::N +
+                            (size_t)M * S::NW * 2);
+}
+
+template <int M>
+__global__ __launch_bounds__(Shape<M>::NT) void unrolled_forward_kernel(FwdParams P)
+{
+    using S = Shape<M>;
+    constexpr int N = S::N, H = S::H, NT = S::NT;
+    extern __shared__ __align__(16) float sm[];
+    float *L = sm;               // column c (2..m+1) at (c-2)*N
+    float *R = sm + M * N;       // two columns, ping-pong by stage parity
+    const int tid = (int)threadIdx.x;
+
+    for (int64_t f = blockIdx.x; f < P.B; f += gridDim.x) {
+        const float *y = P.llr + f * N;
+        for (int i = tid; i < N; i += NT) {
+            for (int c = 0; c < M - 1; c++)
+                L[c * N + i] = 0.0f;
+            L[(M - 1) * N + i] = frozen_at(P.frozen, i) ? kInf : 0.0f;
+        }
+        __syncthreads();
+        for (int t = 0; t < P.T; t++) {
+            if (P.ckpt) {
+                float *ck = P.ckpt + ((int64_t)t * P.B + f) * (M - 1) * N;
+                for (int i = tid; i < (M - 1) * N; i += NT)
+                    ck[i] = L[i];
+            }
+            for (int i = tid; i < N; i += NT)
+                R[i] = y[i];
+            __syncthreads();
+            for (int j = 1; j <= M; j++) {
+                const float aL = P.alpha[((int64_t)t * M + (j - 1)) * 2];
+                const float aR = P.alpha[((int64_t)t * M + (j - 1)) * 2 + 1];
+                const int sh = M - j, h = 1 << sh;
+                if (tid < H) {
+                    const int a = ((tid >> sh) << (sh + 1)) | (tid & (h - 1));
+                    const int b = a + h;
+                    const float *Lc = L + (j - 1) * N;
+                    const float *Ri = R + ((j - 1) & 1) * N;
+                    float *Ro = R + (j & 1) * N;
+                    const float La = Lc[a], Lb = Lc[b];
+                    const float Ra = Ri[a], Rb = Ri[b];
+                    const float s = Lb + Rb;
+                    const float g1 = g0(La, Ra);
+                    if (j >= 2) {
+                        float *Lw = L + (j - 2) * N;
+                        Lw[a] = aL * g0(La, s);
+                        Lw[b] = Lb + aL * g1;
+                    }
+                    Ro[a] = aR * g0(Ra, s);
+                    Ro[b] = Rb + aR * g1;
+                }
+                __syncthreads();
+            }
+        }
+        for (int i = tid; i < N; i += NT)
+            P.out[f * N + i] = R[(M & 1) * N + i];
+        __syncthreads();
+    }
+}
+
+template <int M>
+__global__ __launch_bounds__(Shape<M>::NT) void unrolled_backward_kernel(BwdParams P)
+{
+    using S = Shape<M>;
+    constexpr int N = S::N, H = S::H, NT = S::NT, NW = S::NW;
+    extern __shared__ __align__(16) float sm[];
+    float *Lp = sm;                     // L^{t-1}, column c (2..m+1) at (c-2)*N
+    float *Rc = Lp + M * N;             // R^t, column c (1..m+1) at (c-1)*N
+    float *dL = Rc + (M + 1) * N;       // adjoint of L, column c (2..m) at (c-2)*N
+    float *dR = dL + (M - 1) * N;       // adjoint of R, two columns by parity
+    float *dC = dR + 2 * N;             // adjoint of the channel LLRs
+    float *red = dC + N;                // [m][NW][2] wavefront partial sums
+    const int tid = (int)threadIdx.x;
+    const int lane = tid & 63, wv = tid >> 6;
+
+    for (int64_t f = blockIdx.x; f < P.B; f += gridDim.x) {
+        const float *y = P.llr + f * N;
+        for (int i = tid; i < N; i += NT) {
+            Lp[(M - 1) * N + i] = frozen_at(P.frozen, i) ? kInf : 0.0f;
+            for (int c = 0; c < M - 1; c++)
+                dL[c * N + i] = 0.0f;
+            dC[i] = 0.0f;
+        }
+        for (int t = P.T - 1; t >= 0; t--) {
+            const float *ck = P.ckpt + ((int64_t)t * P.B + f) * (M - 1) * N;
+            for (int i = tid; i < (M - 1) * N; i += NT)
+                Lp[i] = ck[i];
+            for (int i = tid; i < N; i += NT)
+                Rc[i] = y[i];
+            __syncthreads();
+            // the R sweep of iteration t+1
+            for (int j = 1; j <= M; j++) {
+                const float aR = P.alpha[((int64_t)t * M + (j - 1)) * 2 + 1];
+                const int sh = M - j, h = 1 << sh;
+                if (tid < H) {
+                    const int a = ((tid >> sh) << (sh + 1)) | (tid & (h - 1));
+                    const int b = a + h;
+                    const float *Lc = Lp + (j - 1) * N;
+                    const float *Ri = Rc + (j - 1) * N;
+                    float *Ro = Rc + j * N;
+                    const float La = Lc[a], Lb = Lc[b];
+                    const float Ra = Ri[a], Rb = Ri[b];
+                    const float s = Lb + Rb;
+                    Ro[a] = aR * g0(Ra, s);
+                    Ro[b] = Rb + aR * g0(La, Ra);
+                }
+                __syncthreads();
+            }
+            {
+                float *d = dR + ((M + 1) & 1) * N;
+                for (int i = tid; i < N; i += NT)
+                    d[i] = t == P.T - 1 ? P.dout[f * N + i] : 0.0f;
+            }
+            __syncthreads();
+            for (int j = M; j >= 1; j--) {
+                const float aL = P.alpha[((int64_t)t * M + (j - 1)) * 2];
+                const float aR = P.alpha[((int64_t)t * M + (j - 1)) * 2 + 1];
+                const int sh = M - j, h = 1 << sh;
+                float daL = 0.0f, daR = 0.0f;
+                if (tid < H) {
+                    const int a = ((tid >> sh) << (sh + 1)) | (tid & (h - 1));
+                    const int b = a + h;
+                    const float *Lc = Lp + (j - 1) * N;
+                    const float *Ri = Rc + (j - 1) * N;
+                    const float *dRi = dR + ((j + 1) & 1) * N;   // column j+1
+                    float *dRo = dR + (j & 1) * N;               // column j
+                    const float La = Lc[a], Lb = Lc[b];
+                    const float Ra = Ri[a], Rb = Ri[b];
+                    const float s = Lb + Rb;
+                    const float gA = g0(La, s), g1 = g0(La, Ra), gB = g0(Ra, s);
+                    // adjoints of the four outputs; infinite outputs are constants
+                    const bool fLa = finite(aL * gA), fLb = finite(Lb + aL * g1);
+                    const bool fRa = finite(aR * gB), fRb = finite(Rb + aR * g1);
+                    float oLa = 0.0f, oLb = 0.0f;
+                    if (j >= 2) {
+                        const float *dLc = dL + (j - 2) * N;     // column j
+                        oLa = fLa ? dLc[a] : 0.0f;
+                        oLb = fLb ? dLc[b] : 0.0f;
+                    }
+                    const float oRa = fRa ? dRi[a] : 0.0f;
+                    const float oRb = fRb ? dRi[b] : 0.0f;
+                    if (fLa)
+                        daL += oLa * gA;
+                    if (fLb)
+                        daL += oLb * g1;
+                    if (fRa)
+                        daR += oRa * gB;
+                    if (fRb)
+                        daR += oRb * g1;
+                    const float dgA = aL * oLa;
+                    const float dg1 = aL * oLb + aR * oRb;
+                    const float dgB = aR * oRa;
+                    float dLa = 0.0f, dLb = oLb, dRa = 0.0f, dRb = oRb, ds = 0.0f;
+                    g0_back(La, s, dgA, dLa, ds);
+                    g0_back(La, Ra, dg1, dLa, dRa);
+                    g0_back(Ra, s, dgB, dRa, ds);
+                    if (finite(s)) {
+                        dLb += ds;
+                        dRb += ds;
+                    }
+                    if (j + 1 <= M) {
+                        float *dLw = dL + (j - 1) * N;           // column j+1
+                        dLw[a] = finite(La) ? dLa : 0.0f;
+                        dLw[b] = finite(Lb) ? dLb : 0.0f;
+                    }
+                    dRo[a] = dRa;
+                    dRo[b] = dRb;
+                }
+                for (int o = 32; o >= 1; o >>= 1) {
+                    daL += __shfl_xor(daL, o, 64);
+                    daR += __shfl_xor(daR, o, 64);
+                }
+                if (lane == 0) {
+                    red[((j - 1) * NW + wv) * 2] = daL;
+                    red[((j - 1) * NW + wv) * 2 + 1] = daR;
+                }
+                __syncthreads();
+            }
+            for (int i = tid; i < N; i += NT)
+                dC[i] += dR[(1 & 1) * N + i];
+            if (tid < 2 * M) {
+                float acc = 0.0f;
+                for (int w = 0; w < NW; w++)
+                    acc += red[((tid >> 1) * NW + w) * 2 + (tid & 1)];
+                P.dalpha_frame[((f * P.T + t) * M) * 2 + tid] = acc;
+            }
+            __syncthreads();
+        }
+        if (P.dllr)
+            for (int i = tid; i < N; i += NT)
+                P.dllr[f * N + i] = dC[i];
+        __syncthreads();
+    }
+}
+
+// dalpha[k] = sum over frames of dalpha_frame[f][k], in FP64, fixed order
+__global__ __launch_bounds__(256) void reduce_frames_kernel(const float *part,
+                                                            int64_t B, int K,
+                                                            float *out)
+{
+    __shared__ double acc[256];
+    const int k = (int)blockIdx.x, tid = (int)threadIdx.x;
+    double s = 0.0;
+    for (int64_t f = tid; f < B; f += 256)
+        s += (double)part[f * K + k];
+    acc[tid] = s;
+    __syncthreads();
+    for (int w = 128; w >= 1; w >>= 1) {
+        if (tid < w)
+            acc[tid] += acc[tid + w];
+        __syncthreads();
+    }
+    if (tid == 0)
+        out[k] = (float)acc[0];
+}
+
+int64_t frames_grid(const pbp_code *c, int64_t B, int per_cu)
+{
+    int64_t g = (int64_t)(c->cus > 0 ? c->cus : 256) * per_cu;
+    return B < g ? B : g;
+}
+
+template <int M>
+hipError_t launch_forward(const pbp_code *c, FwdParams &P, hipStream_t st)
+{
+    auto kern = unrolled_forward_kernel<M>;
+    const size_t lds = fwd_lds_bytes<M>();
+    hipError_t e = hipFuncSetAttribute((const void *)kern,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)lds);
+    if (e != hipSuccess)
+        return e;
+    hipLaunchKernelGGL(kern, dim3((unsigned)frames_grid(c, P.B, 8)),
+                       dim3(Shape<M>::NT), lds, st, P);
+    return hipGetLastError();
+}
+
+template <int M>
+hipError_t launch_backward(const pbp_code *c, BwdParams &P, hipStream_t st)
+{
+    auto kern = unrolled_backward_kernel<M>;
+    const size_t lds = bwd_lds_bytes<M>();
+    hipError_t e = hipFuncSetAttribute((const void *)kern,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)lds);
+    if (e != hipSuccess)
+        return e;
+    hipLaunchKernelGGL(kern, dim3((unsigned)frames_grid(c, P.B, 4)),
+                       dim3(Shape<M>::NT), lds, st, P);
+    return hipGetLastError();
+}
+
+template <template <int> class Fn, typename Prm>
+hipError_t dispatch_m(int m, const pbp_code *c, Prm &P, hipStream_t st)
+{
+    switch (m) {
+    case 1: return Fn<1>::run(c, P, st);
+    case 2: return Fn<2>::run(c, P, st);
+    case 3: return Fn<3>::run(c, P, st);
+    case 4: return Fn<4>::run(c, P, st);
+    case 5: return Fn<5>::run(c, P, st);
+    case 6: return Fn<6>::run(c, P, st);
+    case 7: return Fn<7>::run(c, P, st);
+    case 8: return Fn<8>::run(c, P, st);
+    case 9: return Fn<9>::run(c, P, st);
+    case 10: return Fn<10>::run(c, P, st);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+template <int M>
+struct Fwd {
+    static hipError_t run(const pbp_code *c, FwdParams &P, hipStream_t st)
+    {
+        return launch_forward<M>(c, P, st);
+    }
+};
+
+template <int M>
+struct Bwd {
+    static hipError_t run(const pbp_code *c, BwdParams &P, hipStream_t st)
+    {
+        return launch_backward<M>(c, P, st);
+    }
+};
+
+constexpr int kMaxUnrolledLog = 10;
+constexpr int kMaxT = 1 << 16;
+
+}  // namespace
+
+extern "C" int32_t pbp_unrolled_forward(const pbp_code *code, const float *llr,
+                                        int64_t B, int32_t T,
+                                        const float *alpha, float *out,
+                                        float *ckpt, void *stream)
+{
+    if (!code || B < 0 || T < 1 || T > kMaxT)
+        return PBP_EINVAL;
+    if (code->m > kMaxUnrolledLog)
+        return PBP_EUNSUPPORTED;
+    if (B == 0)
+        return PBP_OK;
+    if (!llr || !alpha || !out)
+        return PBP_EINVAL;
+    FwdParams P{};
+    P.llr = llr;
+    P.B = B;
+    P.T = T;
+    P.alpha = alpha;
+    P.frozen = code->d_frozen_words;
+    P.out = out;
+    P.ckpt = code->m >= 2 ? ckpt : nullptr;
+    return dispatch_m<Fwd>(code->m, code, P, (hipStream_t)stream) == hipSuccess
+               ? PBP_OK
+               : PBP_EDEVICE;
+}
+
+extern "C" int32_t pbp_unrolled_backward(const pbp_code *code, const float *llr,
+                                         int64_t B, int32_t T,
+                                         const float *alpha, const float *ckpt,
+                                         const float *dout, float *dalpha_frame,
+                                         float *dalpha, float *dllr,
+                                         void *stream)
+{
+    if (!code || B < 0 || T < 1 || T > kMaxT)
+        return PBP_EINVAL;
+    if (code->m > kMaxUnrolledLog)
+        return PBP_EUNSUPPORTED;
+    if (!dalpha)
+        return PBP_EINVAL;
+    hipStream_t st = (hipStream_t)stream;
+    const int K = T * code->m * 2;
+    if (B > 0) {
+        if (!llr || !alpha || !dout || !dalpha_frame ||
+            (code->m >= 2 && !ckpt))
+            return PBP_EINVAL;
+        BwdParams P{};
+        P.llr = llr;
+        P.B = B;
+        P.T = T;
+        P.alpha = alpha;
+        P.frozen = code->d_frozen_words;
+        P.ckpt = ckpt;
+        P.dout = dout;
+        P.dalpha_frame = dalpha_frame;
+        P.dllr = dllr;
+        if (dispatch_m<Bwd>(code->m, code, P, st) != hipSuccess)
+            return PBP_EDEVICE;
+    }
+    hipLaunchKernelGGL(reduce_frames_kernel, dim3((unsigned)K), dim3(256), 0,
+                       st, dalpha_frame, B, K, dalpha);
+    return hipGetLastError() == hipSuccess ? PBP_OK : PBP_EDEVICE;
+}

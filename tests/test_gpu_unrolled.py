@@ -1,0 +1,209 @@
+"""GPU parity of the unrolled decoder and its adjoint against the oracle,
+through the C-ABI.
+
+Bar: forward outputs equal to the FP32 oracle's (same operation order, so
+the same values); gradients within 1e-3 relative (max-norm) of the oracle's
+gradient of the same FP32 forward (accumulated in FP64), and of the FP64
+oracle's, per the tolerance of the unrolled form.
+"""
+
+import numpy as np
+import pytest
+
+import oracle
+from helpers import frozen_mask, make_frames
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1505_04979_amd as pbp
+    pbp.lib()
+    return pbp, torch
+
+
+_codes = {}
+
+
+def code_of(pbp, N, K):
+    if (N, K) not in _codes:
+        _codes[(N, K)] = pbp.Code(N, K, frozen_mask(N, K))
+    return _codes[(N, K)]
+
+
+def rel_err(g, r):
+    g = np.asarray(g, np.float64)
+    r = np.asarray(r, np.float64)
+    return float(np.abs(g - r).max() / max(np.abs(r).max(), 1e-30))
+
+
+def run_gpu(env, N, K, llr, alpha, dout):
+    pbp, torch = env
+    code = code_of(pbp, N, K)
+    d_llr = torch.from_numpy(llr).cuda()
+    d_alpha = torch.from_numpy(alpha.astype(np.float32)).cuda()
+    out, ck = pbp.pbp_unrolled_forward(code, d_llr, d_alpha)
+    da, dl, dfr = pbp.pbp_unrolled_backward(
+        code, d_llr, d_alpha, ck, torch.from_numpy(dout.astype(np.float32)).cuda())
+    torch.cuda.synchronize()
+    return (out.cpu().numpy(), da.cpu().numpy(), dl.cpu().numpy(),
+            dfr.cpu().numpy())
+
+
+CASES = [
+    # N, K, T, B, Eb/N0
+    (2, 1, 4, 64, 1.0),
+    (8, 4, 3, 100, 2.0),
+    (64, 32, 5, 100, 1.5),
+    (128, 64, 20, 64, 2.0),
+    (256, 128, 7, 32, 2.0),
+    (1024, 512, 20, 16, 2.5),
+]
+
+
+@pytest.mark.parametrize("N,K,T,B,ebn0", CASES)
+def test_forward_and_gradient_parity(env, N, K, T, B, ebn0):
+    print(f"[unrolled] N={N} K={K} T={T} B={B}", flush=True)
+    m = N.bit_length() - 1
+    fz = frozen_mask(N, K)
+    _, _, llr = make_frames(N, K, B, ebn0, stream=500 + N)
+    rng = np.random.default_rng(N + T)
+    alpha = rng.uniform(0.6, 1.1, size=(T, m, 2)).astype(np.float32)
+    dout = (rng.standard_normal((B, N)) * (fz == 0)).astype(np.float32)
+    out, da, dl, dfr = run_gpu(env, N, K, llr, alpha, dout)
+    a64 = alpha.astype(np.float64)
+    ref = oracle.unrolled_forward(llr, fz, a64, prec="f32")
+    assert np.array_equal(out, ref)
+    # same FP32 forward, FP64 adjoint
+    rda, rdl = oracle.unrolled_grad(llr, fz, a64, dout, prec="f32")
+    assert rel_err(da, rda) <= 1e-4
+    assert rel_err(dl, rdl) <= 1e-4
+    # per-frame shares add up to the total
+    assert rel_err(dfr.astype(np.float64).sum(axis=0), rda) <= 1e-4
+    # FP64 forward and adjoint
+    rda64, rdl64 = oracle.unrolled_grad(llr, fz, a64, dout, prec="f64")
+    assert rel_err(da, rda64) <= 1e-3
+    assert rel_err(dl, rdl64) <= 1e-3
+
+
+@pytest.mark.parametrize("N,K,T", [(64, 32, 6), (1024, 512, 10)])
+def test_default_scale_equals_plain_decode(env, N, K, T):
+    """With every scale at 0.9375 the unrolled output equals pbp_decode's
+    posterior at the information positions after T plain iterations."""
+    pbp, torch = env
+    m = N.bit_length() - 1
+    fz = frozen_mask(N, K)
+    _, _, llr = make_frames(N, K, 40, 2.0, stream=88)
+    code = code_of(pbp, N, K)
+    d = torch.from_numpy(llr).cuda()
+    alpha = torch.full((T, m, 2), 0.9375, dtype=torch.float32, device="cuda")
+    out, _ = pbp.pbp_unrolled_forward(code, d, alpha, ckpt=False)
+    dec = pbp.pbp_decode(code, d, max_iter=T, early_stop=False, soft=True)
+    torch.cuda.synchronize()
+    info = torch.from_numpy(fz == 0).cuda()
+    assert torch.equal(out[:, info], dec["soft"][:, info])
+
+
+def test_autograd_matches_direct_calls(env):
+    pbp, torch = env
+    N, K, T, B = 128, 64, 20, 256
+    m = 7
+    fz = frozen_mask(N, K)
+    ebn0 = np.random.default_rng(5).uniform(1.0, 4.0, size=B)
+    u, _, llr = make_frames(N, K, B, ebn0, stream=89)
+    code = code_of(pbp, N, K)
+    d_llr = torch.from_numpy(llr).cuda().requires_grad_(True)
+    alpha = torch.full((T, m, 2), 0.9375, dtype=torch.float32,
+                       device="cuda", requires_grad=True)
+    info_pos = torch.from_numpy(np.flatnonzero(fz == 0)).cuda()
+    u_info = torch.from_numpy(u[:, fz == 0].astype(np.float32)).cuda()
+    out = pbp.unrolled_bp(d_llr, alpha, code)
+    loss = pbp.info_bce(out, u_info, info_pos)
+    loss.backward()
+    # the same gradient through the oracle: dloss/dout of the mean BCE
+    z = out.detach().cpu().numpy().astype(np.float64)[:, fz == 0]
+    s = 1.0 - 2.0 * u[:, fz == 0]
+    dz = -s / (1.0 + np.exp(s * z)) / z.size
+    dout = np.zeros((B, N))
+    dout[:, fz == 0] = dz
+    rda, rdl = oracle.unrolled_grad(llr, fz, np.full((T, m, 2), 0.9375), dout,
+                                    prec="f32")
+    assert rel_err(alpha.grad.cpu().numpy(), rda) <= 1e-3
+    assert rel_err(d_llr.grad.cpu().numpy(), rdl) <= 1e-3
+
+
+def test_training_steps_reduce_the_loss(env):
+    """A few plain gradient steps on the scales lower the BCE of a fixed
+    batch (the use the unrolled form exists for)."""
+    pbp, torch = env
+    N, K, T, B = 128, 64, 20, 512
+    m = 7
+    fz = frozen_mask(N, K)
+    ebn0 = np.random.default_rng(6).uniform(1.0, 4.0, size=B)
+    u, _, llr = make_frames(N, K, B, ebn0, stream=90)
+    code = code_of(pbp, N, K)
+    d_llr = torch.from_numpy(llr).cuda()
+    alpha = torch.full((T, m, 2), 0.9375, dtype=torch.float32,
+                       device="cuda", requires_grad=True)
+    info_pos = torch.from_numpy(np.flatnonzero(fz == 0)).cuda()
+    u_info = torch.from_numpy(u[:, fz == 0].astype(np.float32)).cuda()
+    opt = torch.optim.SGD([alpha], lr=0.05)
+    losses = []
+    for _ in range(8):
+        opt.zero_grad()
+        loss = pbp.info_bce(pbp.unrolled_bp(d_llr, alpha, code), u_info,
+                            info_pos)
+        loss.backward()
+        opt.step()
+        losses.append(float(loss.detach()))
+    assert losses[-1] < losses[0]
+
+
+def test_training_batch_shape_sampled(env):
+    """The training configuration (N = 1024, T = 20, 4096 frames, Eb/N0
+    uniform in [1, 4] dB): outputs and per-frame scale gradients of sampled
+    frames against the oracle, and the frame sum."""
+    pbp, torch = env
+    N, K, T, B = 1024, 512, 20, 4096
+    m = 10
+    fz = frozen_mask(N, K)
+    ebn0 = np.random.default_rng(7).uniform(1.0, 4.0, size=B)
+    u, _, llr = make_frames(N, K, B, ebn0, stream=91)
+    rng = np.random.default_rng(8)
+    alpha = rng.uniform(0.8, 1.0, size=(T, m, 2)).astype(np.float32)
+    dout = (rng.standard_normal((B, N)) * (fz == 0)).astype(np.float32)
+    out, da, dl, dfr = run_gpu(env, N, K, llr, alpha, dout)
+    idx = rng.choice(B, 12, replace=False)
+    a64 = alpha.astype(np.float64)
+    ref = oracle.unrolled_forward(llr[idx], fz, a64, prec="f32")
+    assert np.array_equal(out[idx], ref)
+    for f in idx[:6]:
+        rda, rdl = oracle.unrolled_grad(llr[f:f + 1], fz, a64, dout[f:f + 1],
+                                        prec="f32")
+        assert rel_err(dfr[f], rda) <= 1e-4
+        assert rel_err(dl[f:f + 1], rdl) <= 1e-4
+    tot = dfr.astype(np.float64).sum(axis=0)
+    assert np.allclose(da, tot, rtol=1e-6, atol=1e-6 * np.abs(tot).max())
+
+
+def test_rejects_bad_arguments(env):
+    pbp, torch = env
+    code = code_of(pbp, 64, 32)
+    llr = torch.zeros((4, 64), dtype=torch.float32, device="cuda")
+    with pytest.raises(ValueError):
+        pbp.pbp_unrolled_forward(code, llr, torch.ones((3, 5, 2),
+                                                       device="cuda"))
+    big = code_of(pbp, 2048, 1024)
+    with pytest.raises(pbp.PbpError):
+        pbp.pbp_unrolled_forward(
+            big, torch.zeros((1, 2048), dtype=torch.float32, device="cuda"),
+            torch.ones((2, 11, 2), dtype=torch.float32, device="cuda"),
+            ckpt=False)
+    out, _ = pbp.pbp_unrolled_forward(
+        code, torch.zeros((0, 64), dtype=torch.float32, device="cuda"),
+        torch.ones((2, 6, 2), dtype=torch.float32, device="cuda"), ckpt=False)
+    assert out.shape == (0, 64)
