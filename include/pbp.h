@@ -129,6 +129,88 @@ int32_t pbp_decode(const pbp_code *code, const float *llr, int64_t B,
                    int32_t *iters_out, int64_t *pe_out, float *soft_out,
                    void *stream);
 
+/* ---- Mixed-code persistent decoding ----------------------------------
+ * One batch may mix codes of different lengths and rates (each frame names
+ * its code); the whole batch is decoded by one launch of persistent
+ * wavefronts fed by a device work queue.  Decoding per frame is that of
+ * pbp_decode (same results bit for bit); only the schedule differs. */
+
+/* Plan: the codes of a mixed batch, device buffers of the work queue and of
+ * long codes' message state, and the launch configuration.  Calls on one
+ * plan must be ordered on one stream (they share the queue). */
+typedef struct pbp_mixed_plan pbp_mixed_plan;
+
+/* Launch configuration.
+ *  order         0: the queue takes frames in the caller's order;
+ *                1: longest code first (a counting sort on the device)
+ *  waves_per_cu  resident wavefronts per compute unit, 1..8 (each wavefront
+ *                decodes one frame at a time) */
+typedef struct {
+    int32_t order;
+    int32_t waves_per_cu;
+} pbp_mixed_config;
+
+/* Create a plan for up to max_frames frames (1 .. 2^30) over ncodes code
+ * handles (1..16, all on one device; they must outlive the plan).  Device
+ * memory: the queue (4 B per frame) and, when a code has N >= 1024, one
+ * message slot per wavefront ((m+2) 2^m floats for the longest such code).
+ * Default configuration: {1, 8}.  Errors: PBP_EINVAL, PBP_ENOMEM,
+ * PBP_EDEVICE. */
+int32_t pbp_mixed_plan_create(const pbp_code *const *codes, int32_t ncodes,
+                              int64_t max_frames, pbp_mixed_plan **out);
+
+/* Release a plan (NULL is ignored); synchronises its device first. */
+void pbp_mixed_plan_destroy(pbp_mixed_plan *plan);
+
+int32_t pbp_mixed_plan_get_config(const pbp_mixed_plan *plan,
+                                  pbp_mixed_config *cfg);
+/* Errors: PBP_EINVAL for a configuration out of range. */
+int32_t pbp_mixed_plan_set_config(pbp_mixed_plan *plan,
+                                  const pbp_mixed_config *cfg);
+
+/* Decode a mixed batch of B frames (B <= the plan's max_frames).
+ *   code_of_frame  device, B int32: index into the plan's codes.  A frame
+ *                  naming no code of the plan is not decoded: its iteration
+ *                  (and PE) count is set to 0 and its bits are not written.
+ *   llr_off        device, B int64: element offset of the frame's N FP32
+ *                  LLRs in llr (N = 1024 frames at 16-byte aligned
+ *                  addresses take the register-resident decoder)
+ *   info_off       device, B int64: byte offset of the frame's K decided
+ *                  information bits in info_out
+ *   llr            device FP32 LLR buffer (finite)
+ *   opts           host, as for pbp_decode
+ *   iters_out      device, B int32; pe_out device, B int64, or NULL
+ * Ranges given by the offsets must lie inside the caller's buffers; output
+ * ranges of different frames must not overlap.  Enqueues a few small
+ * kernels (order 1) and one persistent kernel; no allocation, no memset, no
+ * host synchronisation, so the call can be captured in a HIP graph and
+ * replayed (the queue rewinds itself at the end of every launch).
+ * Errors: PBP_EINVAL, PBP_EDEVICE. */
+int32_t pbp_decode_mixed(pbp_mixed_plan *plan, const int32_t *code_of_frame,
+                         const int64_t *llr_off, const int64_t *info_off,
+                         int64_t B, const float *llr,
+                         const pbp_decode_opts *opts, uint8_t *info_out,
+                         int32_t *iters_out, int64_t *pe_out, void *stream);
+
+/* Autotuner: time every candidate configuration (order 0/1 x 2, 4, 6 or 8
+ * wavefronts per compute unit) on the given batch, one untimed and `reps`
+ * timed launches each, and keep the fastest in the plan (also written to
+ * *best if not NULL).  Results are cached for the life of the process per
+ * (device, the plan's (N, K) list, early_stop, freezing): a later call with
+ * the same key launches nothing.  The batch's outputs are overwritten.
+ * Synchronous.  Errors: as pbp_decode_mixed, PBP_EINVAL for reps < 1. */
+int32_t pbp_mixed_plan_tune(pbp_mixed_plan *plan, const int32_t *code_of_frame,
+                            const int64_t *llr_off, const int64_t *info_off,
+                            int64_t B, const float *llr,
+                            const pbp_decode_opts *opts, uint8_t *info_out,
+                            int32_t *iters_out, int64_t *pe_out, int32_t reps,
+                            void *stream, pbp_mixed_config *best);
+
+/* Fill efficiency of the plan's last launch: the wavefronts' time spent
+ * decoding over (wavefronts x the launch's span), from device timestamps.
+ * Synchronises `stream` first.  Errors: PBP_EINVAL, PBP_EDEVICE. */
+int32_t pbp_mixed_plan_fill(pbp_mixed_plan *plan, void *stream, double *fill);
+
 /* Unrolled BP with trainable scales (the decoder of eq. (1) unrolled over T
  * iterations, single sweep, no early stop and no freezing), for learning the
  * min-sum scale per iteration, stage and direction.  Iteration t, stage j:

@@ -26,6 +26,10 @@ class pbp_decode_opts(ctypes.Structure):
                 ("freeze_walk", ctypes.c_int32), ("alpha", ctypes.c_float)]
 
 
+class pbp_mixed_config(ctypes.Structure):
+    _fields_ = [("order", ctypes.c_int32), ("waves_per_cu", ctypes.c_int32)]
+
+
 class PbpError(RuntimeError):
     def __init__(self, fn, status):
         self.status = status
@@ -47,6 +51,21 @@ _SIGNATURES = [
     ("pbp_decode", ctypes.c_int32,
      [_P, _P, ctypes.c_int64, ctypes.POINTER(pbp_decode_opts), _P, _P, _P, _P,
       _P]),
+    ("pbp_mixed_plan_create", ctypes.c_int32,
+     [_P, ctypes.c_int32, ctypes.c_int64, ctypes.POINTER(_P)]),
+    ("pbp_mixed_plan_destroy", None, [_P]),
+    ("pbp_mixed_plan_get_config", ctypes.c_int32,
+     [_P, ctypes.POINTER(pbp_mixed_config)]),
+    ("pbp_mixed_plan_set_config", ctypes.c_int32,
+     [_P, ctypes.POINTER(pbp_mixed_config)]),
+    ("pbp_decode_mixed", ctypes.c_int32,
+     [_P, _P, _P, _P, ctypes.c_int64, _P, ctypes.POINTER(pbp_decode_opts), _P,
+      _P, _P, _P]),
+    ("pbp_mixed_plan_tune", ctypes.c_int32,
+     [_P, _P, _P, _P, ctypes.c_int64, _P, ctypes.POINTER(pbp_decode_opts), _P,
+      _P, _P, ctypes.c_int32, _P, ctypes.POINTER(pbp_mixed_config)]),
+    ("pbp_mixed_plan_fill", ctypes.c_int32,
+     [_P, _P, ctypes.POINTER(ctypes.c_double)]),
     ("pbp_unrolled_forward", ctypes.c_int32,
      [_P, _P, ctypes.c_int64, ctypes.c_int32, _P, _P, _P, _P]),
     ("pbp_unrolled_backward", ctypes.c_int32,
@@ -264,3 +283,112 @@ def pbp_unrolled_backward(code, llr, alpha, ckpt, dout, dllr=True,
         _dev_ptr(dllr, torch.float32, (B, N), "dllr"),
         _stream(stream)))
     return dalpha, dllr, dframe
+
+
+class MixedPlan:
+    """Owns a pbp_mixed_plan over a list of Code objects (kept alive here)."""
+
+    def __init__(self, codes, max_frames):
+        self.codes = list(codes)
+        arr = (_P * len(self.codes))(*[c.handle for c in self.codes])
+        h = _P()
+        _check("pbp_mixed_plan_create", lib().pbp_mixed_plan_create(
+            arr, len(self.codes), int(max_frames), ctypes.byref(h)))
+        self._h = h
+        self.max_frames = int(max_frames)
+
+    @property
+    def handle(self):
+        return self._h
+
+    @property
+    def config(self):
+        c = pbp_mixed_config()
+        _check("pbp_mixed_plan_get_config",
+               lib().pbp_mixed_plan_get_config(self._h, ctypes.byref(c)))
+        return (c.order, c.waves_per_cu)
+
+    @config.setter
+    def config(self, value):
+        c = pbp_mixed_config(int(value[0]), int(value[1]))
+        _check("pbp_mixed_plan_set_config",
+               lib().pbp_mixed_plan_set_config(self._h, ctypes.byref(c)))
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().pbp_mixed_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def pbp_mixed_plan_create(codes, max_frames):
+    return MixedPlan(codes, max_frames)
+
+
+def _mixed_args(plan, code_of_frame, llr_off, info_off, llr, info_bytes,
+                opts, pe, out, kw):
+    import torch
+    if opts is None:
+        opts = make_opts(**kw)
+    B = int(code_of_frame.shape[0])
+    dev = code_of_frame.device
+    o = dict(out or {})
+    if "info" not in o:
+        o["info"] = torch.empty((int(info_bytes),), dtype=torch.uint8,
+                                device=dev)
+    if "iters" not in o:
+        o["iters"] = torch.empty((B,), dtype=torch.int32, device=dev)
+    if pe and "pe" not in o:
+        o["pe"] = torch.empty((B,), dtype=torch.int64, device=dev)
+    if llr.dim() != 1:
+        raise ValueError("llr must be a flat buffer")
+    args = (_dev_ptr(code_of_frame, torch.int32, (B,), "code_of_frame"),
+            _dev_ptr(llr_off, torch.int64, (B,), "llr_off"),
+            _dev_ptr(info_off, torch.int64, (B,), "info_off"), B,
+            _dev_ptr(llr, torch.float32, tuple(llr.shape), "llr"),
+            ctypes.byref(opts),
+            _dev_ptr(o["info"], torch.uint8, tuple(o["info"].shape), "info"),
+            _dev_ptr(o["iters"], torch.int32, (B,), "iters"),
+            _dev_ptr(o.get("pe") if pe else None, torch.int64, (B,), "pe"))
+    return args, o
+
+
+def pbp_decode_mixed(plan, code_of_frame, llr_off, info_off, llr,
+                     info_bytes=None, opts=None, pe=True, out=None,
+                     stream=None, **kw):
+    """Decode a mixed batch: frame f of code ``codes[code_of_frame[f]]`` has
+    its LLRs at ``llr[llr_off[f]:]`` (flat float32 buffer) and its decided
+    information bits go to ``info[info_off[f]:]`` (flat uint8 buffer of
+    ``info_bytes`` bytes, or ``out["info"]``).  Returns a dict of device
+    tensors ``info``, ``iters`` and (when asked) ``pe``."""
+    args, o = _mixed_args(plan, code_of_frame, llr_off, info_off, llr,
+                          info_bytes, opts, pe, out, kw)
+    _check("pbp_decode_mixed", lib().pbp_decode_mixed(
+        plan.handle, *args, _stream(stream)))
+    return o
+
+
+def pbp_mixed_plan_tune(plan, code_of_frame, llr_off, info_off, llr,
+                        info_bytes=None, opts=None, pe=True, out=None,
+                        reps=2, stream=None, **kw):
+    """Choose the plan's configuration by timing the candidates on this
+    batch (outputs overwritten); returns (order, waves_per_cu)."""
+    args, o = _mixed_args(plan, code_of_frame, llr_off, info_off, llr,
+                          info_bytes, opts, pe, out, kw)
+    best = pbp_mixed_config()
+    _check("pbp_mixed_plan_tune", lib().pbp_mixed_plan_tune(
+        plan.handle, *args, int(reps), _stream(stream), ctypes.byref(best)))
+    return (best.order, best.waves_per_cu)
+
+
+def pbp_mixed_plan_fill(plan, stream=None):
+    """Fill efficiency of the plan's last launch (synchronises the stream)."""
+    v = ctypes.c_double()
+    _check("pbp_mixed_plan_fill", lib().pbp_mixed_plan_fill(
+        plan.handle, _stream(stream), ctypes.byref(v)))
+    return v.value

@@ -22,12 +22,13 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libpbp.so")
-SOURCES = ["pbp_host.cpp", "pbp_decode.hip", "pbp_r10.hip", "pbp_unrolled.hip"]
+SOURCES = ["pbp_host.cpp", "pbp_decode.hip", "pbp_r10.hip", "pbp_unrolled.hip",
+           "pbp_mixed.hip"]
 
 HIPCC = os.environ.get("HIPCC", shutil.which("hipcc") or "/opt/rocm/bin/hipcc")
 ARCH = os.environ.get("PBP_OFFLOAD_ARCH", "gfx950")
 
-FLAGS = ["-O3", "-std=c++17", f"--offload-arch={ARCH}", "-fPIC", "-shared",
+FLAGS = ["-O3", "-std=c++17", f"--offload-arch={ARCH}", "-fPIC",
          "-ffp-contract=off", "-fno-fast-math",
          # device code: messages are never NaN, so the min of eq. (1) needs no
          # signalling-NaN quieting (IEEE mode off)
@@ -36,13 +37,30 @@ FLAGS = ["-O3", "-std=c++17", f"--offload-arch={ARCH}", "-fPIC", "-shared",
          "-Wall", "-Wno-unused-result"]
 
 
+def _compile(src, obj, verbose):
+    cmd = [HIPCC] + FLAGS + ["-c", "-I", INCLUDE, "-I", CSRC]
+    cmd += (["-x", "hip", src] if src.endswith(".cpp") else [src])
+    cmd += ["-o", obj]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.run(cmd, check=True)
+
+
 def build(verbose=False):
-    srcs = []
-    for s in SOURCES:
-        p = os.path.join(CSRC, s)
-        srcs += (["-x", "hip", p] if s.endswith(".cpp") else [p])
+    """Compile every source to an object (in parallel), then link."""
+    from concurrent.futures import ThreadPoolExecutor
+    objdir = os.path.join(HERE, "_build")
+    os.makedirs(objdir, exist_ok=True)
+    objs = [os.path.join(objdir, os.path.splitext(s)[0] + ".o")
+            for s in SOURCES]
+    jobs = max(1, min(len(SOURCES), os.cpu_count() or 1, 16))
+    with ThreadPoolExecutor(jobs) as ex:
+        for f in [ex.submit(_compile, os.path.join(CSRC, s), o, verbose)
+                  for s, o in zip(SOURCES, objs)]:
+            f.result()
     tmp = LIB + ".tmp"
-    cmd = [HIPCC] + FLAGS + ["-I", INCLUDE, "-I", CSRC] + srcs + ["-o", tmp]
+    cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC"] + objs + \
+        ["-o", tmp]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)

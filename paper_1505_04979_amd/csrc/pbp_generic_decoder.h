@@ -1,0 +1,404 @@
+// Generic BP decoder of one frame (any N = 2^m, m <= 14), shared by the
+// batch kernel (pbp_decode.hip) and the mixed-code persistent kernel
+// (pbp_mixed.hip).
+//
+// The left-to-right messages live in one working column updated in place
+// stage by stage (stage j reads R at column j and writes R at column j+1 on
+// the same rows), the channel LLRs in a second column, and the
+// right-to-left messages L at columns 1..m+1.  Placement (STATE): 0 = all in
+// LDS; 1 = L in a device-memory slot, the two R columns in LDS; 2 = L and
+// the working R column in the slot, channel LLRs read in place.  Hard
+// decisions are packed 64 to a word with wavefront ballots; the transform by
+// F^{(x)s} runs on those words (shift/mask/xor inside a word, xor across
+// words by cross-lane shuffles).  The CSFG walk and the stop test run on
+// wavefront 0.  WAVE: the frame is decoded by one wavefront alone (ordering
+// by wavefront barriers), else by the whole workgroup.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "pbp_internal.h"
+
+namespace pbp {
+namespace generic {
+namespace {
+
+constexpr float kInf = __builtin_inff();
+
+// The min-sum term of eq. (1): alpha * sign(x) * sign(y) * min(|x|, |y|).
+// A zero result may carry either sign; no value or decision depends on it.
+__device__ __forceinline__ float gmin(float x, float y, float alpha)
+{
+    // sign(x) sign(y) min(|x|, |y|) is y, its sign flipped when x < 0,
+    // clamped to [-|x|, |x|]: one median of three (exact, a selection); the
+    // product with alpha then rounds once, symmetrically in sign
+    const float t = __uint_as_float(__float_as_uint(y) ^
+                                    (__float_as_uint(x) & 0x80000000u));
+    return alpha * __builtin_amdgcn_fmed3f(-fabsf(x), t, fabsf(x));
+}
+
+// x F^{(x)6} over the 64 bits of a word (bit i = position i): at each level
+// hh, position i with bit hh clear takes x[i] ^ x[i + hh].
+__device__ __forceinline__ uint64_t ffx_word(uint64_t x)
+{
+    x ^= (x >> 1) & 0x5555555555555555ull;
+    x ^= (x >> 2) & 0x3333333333333333ull;
+    x ^= (x >> 4) & 0x0F0F0F0F0F0F0F0Full;
+    x ^= (x >> 8) & 0x00FF00FF00FF00FFull;
+    x ^= (x >> 16) & 0x0000FFFF0000FFFFull;
+    x ^= (x >> 32) & 0x00000000FFFFFFFFull;
+    return x;
+}
+
+__device__ __forceinline__ uint64_t shfl_xor64(uint64_t v, int mask)
+{
+    const int lo = __shfl_xor((int)(uint32_t)v, mask, 64);
+    const int hi = __shfl_xor((int)(uint32_t)(v >> 32), mask, 64);
+    return ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo;
+}
+
+// Order LDS traffic between the lanes of one wavefront.
+__device__ __forceinline__ void wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Up to 4 words per lane: blocks of at most 16384 bits.
+constexpr int kMaxWordsPerLane = 4;
+
+// In-register F^{(x)s} transform of nw words (nw a power of two, word w =
+// lane + 64 q held in r[q]); each word already transformed internally.
+__device__ __forceinline__ void ffx_cross(uint64_t (&r)[kMaxWordsPerLane],
+                                          int nw, int lane)
+{
+    for (int L = 1; L < nw && L < 64; L <<= 1) {
+#pragma unroll
+        for (int q = 0; q < kMaxWordsPerLane; q++) {
+            const uint64_t o = shfl_xor64(r[q], L);
+            if (!(lane & L))
+                r[q] ^= o;
+        }
+    }
+    if (nw > 64) {
+        // word distance 64: q with bit 0 clear takes q+1; distance 128: q in
+        // {0,1} takes q+2
+        r[0] ^= r[1];
+        r[2] ^= r[3];
+        if (nw > 128) {
+            r[0] ^= r[2];
+            r[1] ^= r[3];
+        }
+    }
+}
+
+struct DecodeParams {
+    const float *llr;
+    int64_t B;
+    const uint64_t *frozen_words;
+    const int32_t *info_pos;
+    int32_t K;
+    int32_t max_iter, early_stop, freezing, freeze_input, freeze_walk;
+    float alpha;
+    uint8_t *info_out;
+    int32_t *iters_out;
+    int64_t *pe_out;
+    float *soft_out;
+    float *state;          // global L state (when not in LDS)
+    int64_t state_stride;  // floats per workgroup slot
+};
+
+// Control words kept in LDS.
+struct Ctl {
+    int p[16];        // p[j]: number of frozen CSFGs at stage j (p[0] = 0)
+    int stop;
+    int walking;
+};
+
+template <int M>
+struct Layout {
+    static constexpr int N = 1 << M;
+    static constexpr int NW = N >= 64 ? N / 64 : 1;   // bit words per frame
+};
+
+__device__ __forceinline__ bool frozen_bit(const uint64_t *fw, int i)
+{
+    return (fw[i >> 6] >> (i & 63)) & 1;
+}
+
+template <bool WAVE>
+__device__ __forceinline__ void sync()
+{
+    if constexpr (WAVE)
+        wave_sync();
+    else
+        __syncthreads();
+}
+
+// LDS bytes of one decoder instance: [u64 xw NW][u64 dw NW][Ctl], then
+// [f32 Rw N][f32 ch N] unless STATE == 2, then L (m+1 columns) if STATE == 0
+template <int M>
+__host__ __device__ constexpr size_t lds_bytes(int state)
+{
+    return 2 * sizeof(uint64_t) * Layout<M>::NW + sizeof(Ctl) +
+           (state < 2 ? 2 * sizeof(float) * (1u << M) : 0) +
+           (state == 0 ? sizeof(float) * (size_t)(M + 1) * (1u << M) : 0);
+}
+
+// floats of a device-memory slot: L (m+1 columns), plus the working R
+// column when STATE == 2
+template <int M>
+__host__ __device__ constexpr int64_t slot_floats(int state)
+{
+    return (int64_t)(M + 1 + (state == 2 ? 1 : 0)) << M;
+}
+
+// Decode frame `frame` of P (LLRs at P.llr + frame N, outputs at index
+// frame).  smem: this instance's LDS (lds_bytes); gslot: its device slot
+// (slot_floats, STATE > 0).  tid, NT: thread index and count of the group
+// decoding the frame (NT = 64 when WAVE).
+template <int M, int STATE, bool WAVE>
+__device__ __forceinline__ void decode_frame(const DecodeParams &P,
+                                             int64_t frame,
+                                             unsigned char *smem,
+                                             float *gslot, int tid, int NT)
+{
+    constexpr int N = 1 << M;
+    constexpr int NW = Layout<M>::NW;
+    uint64_t *xw = reinterpret_cast<uint64_t *>(smem);
+    uint64_t *dw = xw + NW;
+    Ctl *ctl = reinterpret_cast<Ctl *>(dw + NW);
+    float *Rw = STATE == 2 ? gslot + (int64_t)(M + 1) * N
+                           : reinterpret_cast<float *>(ctl + 1);
+    float *chl = reinterpret_cast<float *>(ctl + 1) + N;
+    float *Lbase = STATE == 0 ? chl + N : gslot;
+    // L at column c (1..M+1)
+    auto Lc = [&](int c) { return Lbase + (size_t)(c - 1) * N; };
+    const int lane = tid & 63;
+    const bool wave0 = tid < 64;
+    const float alpha = P.alpha;
+    // an opaque thread count keeps the strided loops rolled (a known count
+    // of 64 would unroll them N/64 times over and exhaust the registers)
+    NT = __builtin_amdgcn_readfirstlane(NT);
+    asm volatile("" : "+s"(NT));
+
+    const float *llr = P.llr + frame * N;
+    const float *ch = STATE == 2 ? llr : chl;
+    // ---- initial messages ----
+    for (int i = tid; i < N; i += NT) {
+        if (STATE != 2)
+            chl[i] = llr[i];
+        for (int c = 1; c <= M; c++)
+            Lc(c)[i] = 0.0f;
+        Lc(M + 1)[i] = frozen_bit(P.frozen_words, i) ? kInf : 0.0f;
+    }
+    for (int w = tid; w < NW; w += NT)
+        dw[w] = 0;
+    if (tid == 0) {
+        for (int j = 0; j <= M; j++)
+            ctl->p[j] = 0;
+        ctl->stop = 0;
+    }
+    sync<WAVE>();
+
+    int64_t pe = 0;
+    int t = 1;
+    for (; t <= P.max_iter; t++) {
+        if (tid == 0)
+            ctl->walking = 1;
+        for (int j = 1; j <= M; j++) {
+            const int s = M - j;
+            const int h = 1 << s;
+            const int f = ctl->p[j - 1] << (s + 1);  // frozen rows, column j
+            const float *Rin = (j == 1) ? ch : Rw;
+            float *Lj = Lc(j);
+            const float *Lj1 = Lc(j + 1);
+            // ---- PE updates, eq. (1) ----
+            for (int q = (f >> 1) + tid; q < N / 2; q += NT) {
+                const int a = ((q >> s) << (s + 1)) | (q & (h - 1));
+                const int b = a + h;
+                const float La = Lj1[a], Lb = Lj1[b];
+                const float Ra = Rin[a], Rb = Rin[b];
+                const float sm = Lb + Rb;
+                const float g1 = gmin(La, Ra, alpha);
+                Lj[a] = gmin(La, sm, alpha);
+                Lj[b] = Lb + g1;
+                Rw[a] = gmin(Ra, sm, alpha);
+                Rw[b] = Rb + g1;
+            }
+            pe += (N - f) >> 1;
+            sync<WAVE>();
+            if (!P.freezing)
+                continue;
+            // ---- CSFG freezing walk (Section III), wavefront 0 ----
+            if (wave0) {
+                int pj = max(ctl->p[j], 2 * ctl->p[j - 1]);
+                int walking = ctl->walking;
+                float *L1 = Lc(j + 1);
+                const int nw = h >= 64 ? h >> 6 : 1;
+                while (pj < (1 << j) && (P.freeze_walk != 0 || walking)) {
+                    const int r0 = pj << s;
+                    // eq. (2): hard decisions of the CSFG's inputs
+                    for (int w = 0; w < nw; w++) {
+                        const int i = 64 * w + lane;
+                        bool x = false;
+                        if (i < h) {
+                            const float v = P.freeze_input
+                                                ? Rw[r0 + i] + L1[r0 + i]
+                                                : Rw[r0 + i];
+                            x = v < 0.0f;
+                        }
+                        const uint64_t bal = __ballot(x);
+                        if (lane == 0)
+                            xw[w] = bal;
+                    }
+                    sync<true>();
+                    // eq. (3): uhat = xhat F^{(x)s}
+                    uint64_t r[kMaxWordsPerLane];
+#pragma unroll
+                    for (int q = 0; q < kMaxWordsPerLane; q++) {
+                        const int w = lane + 64 * q;
+                        r[q] = w < nw ? ffx_word(xw[w]) : 0;
+                    }
+                    ffx_cross(r, nw, lane);
+                    // eq. (4): no frozen position may decode to 1
+                    bool bad = false;
+#pragma unroll
+                    for (int q = 0; q < kMaxWordsPerLane; q++) {
+                        const int w = lane + 64 * q;
+                        if (w < nw) {
+                            uint64_t fz;
+                            if (h >= 64) {
+                                fz = P.frozen_words[(r0 >> 6) + w];
+                            } else {
+                                fz = (P.frozen_words[r0 >> 6] >> (r0 & 63)) &
+                                     ((1ull << h) - 1);
+                            }
+                            bad |= (r[q] & fz) != 0;
+                        }
+                    }
+                    if (__any(bad))
+                        break;
+                    // freeze: L at column j+1 := (-1)^xhat inf, keep uhat
+#pragma unroll
+                    for (int q = 0; q < kMaxWordsPerLane; q++) {
+                        const int w = lane + 64 * q;
+                        if (w < nw) {
+                            // a CSFG may cover sub-CSFGs of later
+                            // stages frozen before it: its decisions
+                            // replace theirs
+                            if (h >= 64) {
+                                dw[(r0 >> 6) + w] = r[q];
+                            } else {
+                                const uint64_t msk = ((1ull << h) - 1)
+                                                     << (r0 & 63);
+                                dw[r0 >> 6] = (dw[r0 >> 6] & ~msk) |
+                                              (r[q] << (r0 & 63));
+                            }
+                        }
+                    }
+                    for (int i = lane; i < h; i += 64) {
+                        const bool x = (xw[i >> 6] >> (i & 63)) & 1;
+                        L1[r0 + i] = x ? -kInf : kInf;
+                    }
+                    sync<true>();
+                    pj++;
+                    if (P.freeze_walk == 0) {
+                        walking = 0;
+                        break;
+                    }
+                    if (P.freeze_walk == 1)
+                        break;
+                }
+                if (lane == 0) {
+                    ctl->p[j] = pj;
+                    ctl->walking = walking;
+                }
+            }
+            sync<WAVE>();
+        }
+
+        // ---- decisions, termination ----
+        const int fm = P.freezing ? ctl->p[M] : 0;
+        if (wave0) {
+            int stop = P.freezing && fm == N;
+            if (!stop && P.early_stop) {
+                // G-matrix criterion: uhat F^{(x)m} == hard(R + L) at
+                // column 1
+                const float *L1 = Lc(1);
+                uint64_t r[kMaxWordsPerLane];
+                for (int w = 0; w < NW; w++) {
+                    const int i = 64 * w + lane;
+                    bool u = false;
+                    if (i < N) {
+                        if (i < fm)
+                            u = (dw[i >> 6] >> (i & 63)) & 1;
+                        else
+                            u = !frozen_bit(P.frozen_words, i) && Rw[i] < 0.0f;
+                    }
+                    const uint64_t bal = __ballot(u);
+                    if (lane == 0)
+                        xw[w] = bal;
+                }
+                sync<true>();
+#pragma unroll
+                for (int q = 0; q < kMaxWordsPerLane; q++) {
+                    const int w = lane + 64 * q;
+                    r[q] = w < NW ? ffx_word(xw[w]) : 0;
+                }
+                ffx_cross(r, NW, lane);
+                bool diff = false;
+                for (int w = 0; w < NW; w++) {
+                    const int i = 64 * w + lane;
+                    const bool x = i < N && (ch[i] + L1[i] < 0.0f);
+                    const uint64_t bal = __ballot(x);
+                    // the lane holding word w compares it
+                    if ((w & 63) == lane) {
+                        const int q = w >> 6;
+                        uint64_t mine = r[0];
+                        if (q == 1) mine = r[1];
+                        if (q == 2) mine = r[2];
+                        if (q == 3) mine = r[3];
+                        diff |= mine != bal;
+                    }
+                }
+                stop = !__any(diff);
+            }
+            if (lane == 0)
+                ctl->stop = stop;
+        }
+        sync<WAVE>();
+        if (ctl->stop)
+            break;
+    }
+    if (t > P.max_iter)
+        t = P.max_iter;
+
+    // ---- outputs ----
+    const int fm = P.freezing ? ctl->p[M] : 0;
+    uint8_t *out = P.info_out + frame * P.K;
+    for (int k = tid; k < P.K; k += NT) {
+        const int i = P.info_pos[k];
+        out[k] = i < fm ? (uint8_t)((dw[i >> 6] >> (i & 63)) & 1)
+                        : (uint8_t)(Rw[i] < 0.0f);
+    }
+    if (P.soft_out) {
+        float *so = P.soft_out + frame * N;
+        const float *Lm = Lc(M + 1);
+        for (int i = tid; i < N; i += NT)
+            so[i] = i < fm ? (((dw[i >> 6] >> (i & 63)) & 1) ? -kInf : kInf)
+                           : Rw[i] + Lm[i];
+    }
+    if (tid == 0) {
+        P.iters_out[frame] = t;
+        if (P.pe_out)
+            P.pe_out[frame] = pe;
+    }
+    sync<WAVE>();
+}
+
+}  // namespace
+}  // namespace generic
+}  // namespace pbp

@@ -1,0 +1,608 @@
+// Persistent decoding of a batch that mixes codes (lengths and rates).
+//
+// The work queue is built on the device: a counting sort groups the frames
+// by code (an order array of frame indices, one contiguous segment per
+// code).  Each code's segment is then drained by its own persistent kernel,
+// specialised for that code length: a pool of wavefronts, each taking the
+// next queue entry from a device counter, reading the frame's buffer
+// offsets and decoding the whole frame alone -- N = 1024 with the
+// register-resident decoder, N <= 512 with the generic decoder and its state
+// in the wavefront's LDS, N >= 2048 with the generic decoder and its state in
+// the wavefront's device-memory slot.  The last wavefront out of a kernel
+// rewinds its counter, so the enqueued work needs no host-side or memset
+// reset and can be captured in a graph and replayed.
+//
+// Configuration: the order in which the code segments are drained (longest
+// code first or shortest first) and the number of resident wavefronts per
+// compute unit, set by the caller or chosen by timing the candidates on a
+// sample batch (pbp_mixed_plan_tune), with results cached per device, code
+// set and mode for the life of the process.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <map>
+#include <mutex>
+#include <new>
+#include <tuple>
+#include <vector>
+
+#include "pbp.h"
+#include "pbp_generic_decoder.h"
+#include "pbp_internal.h"
+#include "pbp_r10.h"
+#include "pbp_r10_decoder.h"
+
+namespace {
+
+constexpr int kMaxCodes = 16;
+constexpr int kMaxWavesPerCu = 8;
+constexpr int64_t kMaxFrames = 1ll << 30;
+
+struct CodeDesc {
+    int32_t m, K;
+    const uint64_t *frozen_words;
+    const int32_t *info_pos;
+    const uint64_t *fzw10;      // N = 1024 register decoder words, or null
+};
+
+// One code's share of a mixed launch.
+struct ClassParams {
+    CodeDesc code;
+    const int *bounds;          // bucket starts (bounds[b] .. bounds[b+1])
+    int32_t bucket;
+    const int32_t *order;       // queue position -> frame
+    const int64_t *llr_off;
+    const int64_t *info_off;
+    const float *llr;
+    int32_t max_iter, early_stop, freezing, freeze_input, freeze_walk;
+    float alpha;
+    uint8_t *info_out;
+    int32_t *iters_out;
+    int64_t *pe_out;
+    int *counter;               // [queue head, waves out] of this code
+    float *state;               // device slots (long codes)
+    int64_t slot_floats;
+    int64_t *stats;             // per wavefront: start, end, busy (ticks)
+};
+
+using pbp::generic::DecodeParams;
+using pbp::generic::decode_frame;
+
+// PATH: 0 = generic decoder, state in LDS; 2 = generic decoder, state in a
+// device slot; 10 = register decoder with early stop; 11 = register decoder
+// without early stop (freezing switched at run time)
+template <int M, int PATH>
+__global__ __launch_bounds__(64, 2) void class_kernel(ClassParams P)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int lane = (int)__builtin_amdgcn_workitem_id_x();
+    const int64_t wave = blockIdx.x;
+    float *gslot = PATH == 2 ? P.state + wave * P.slot_floats : nullptr;
+    const int lo = P.bounds[P.bucket], hi = P.bounds[P.bucket + 1];
+    const int64_t t_start = wall_clock64();
+    int64_t busy = 0;
+    for (;;) {
+        int q = 0;
+        if (lane == 0)
+            q = atomicAdd(P.counter, 1);
+        q = __builtin_amdgcn_readfirstlane(__shfl(q, 0, 64)) + lo;
+        if (q >= hi)
+            break;
+        const int64_t t0 = wall_clock64();
+        const int f = __builtin_amdgcn_readfirstlane(P.order[q]);
+        const float *llr = P.llr + P.llr_off[f];
+        uint8_t *info = P.info_out + P.info_off[f];
+        if constexpr (PATH >= 10) {
+            pbp::r10::Params R{};
+            R.llr = llr;
+            R.B = 1;
+            R.fzw = P.code.fzw10;
+            R.info_pos = P.code.info_pos;
+            R.K = P.code.K;
+            R.max_iter = P.max_iter;
+            R.freezing = P.freezing;
+            R.freeze_input = P.freeze_input;
+            R.freeze_walk = P.freeze_walk;
+            R.alpha = P.alpha;
+            R.info_out = info;
+            R.iters_out = P.iters_out + f;
+            R.pe_out = P.pe_out ? P.pe_out + f : nullptr;
+            R.soft_out = nullptr;
+            pbp::r10::Decoder<true, PATH == 10> D(
+                R, *reinterpret_cast<pbp::r10::Smem *>(smem), lane);
+            D.decode(0);
+        } else {
+            DecodeParams D{};
+            D.llr = llr;
+            D.B = 1;
+            D.frozen_words = P.code.frozen_words;
+            D.info_pos = P.code.info_pos;
+            D.K = P.code.K;
+            D.max_iter = P.max_iter;
+            D.early_stop = P.early_stop;
+            D.freezing = P.freezing;
+            D.freeze_input = P.freeze_input;
+            D.freeze_walk = P.freeze_walk;
+            D.alpha = P.alpha;
+            D.info_out = info;
+            D.iters_out = P.iters_out + f;
+            D.pe_out = P.pe_out ? P.pe_out + f : nullptr;
+            D.soft_out = nullptr;
+            decode_frame<M, PATH, true>(D, 0, smem, gslot, lane, 64);
+        }
+        busy += wall_clock64() - t0;
+    }
+    if (lane == 0) {
+        P.stats[wave * 3] = t_start;
+        P.stats[wave * 3 + 1] = wall_clock64();
+        P.stats[wave * 3 + 2] = busy;
+        // every wavefront has taken its last queue entry before it counts
+        // itself out; the last one out rewinds both counters
+        if (atomicAdd(P.counter + 1, 1) == (int)gridDim.x - 1) {
+            atomicExch(P.counter, 0);
+            atomicExch(P.counter + 1, 0);
+        }
+    }
+}
+
+// ---- the work queue: frames grouped by code (counting sort) ----
+
+struct CodeSet {
+    int32_t m[kMaxCodes];
+    int32_t ncodes;
+};
+
+// frame f's bucket: its code, or ncodes for a frame that is not decoded (a
+// code index outside the plan, or N = 1024 LLRs that are not 16-byte
+// aligned); such frames get zero iterations and PE updates here
+__device__ __forceinline__ int bucket_of(const CodeSet &cs, const int32_t *code_of_frame,
+                                         const int64_t *llr_off, const float *llr,
+                                         int f)
+{
+    const int c = code_of_frame[f];
+    if (c < 0 || c >= cs.ncodes)
+        return cs.ncodes;
+    if (cs.m[c] == pbp::r10::M &&
+        (reinterpret_cast<uintptr_t>(llr + llr_off[f]) & 15))
+        return cs.ncodes;
+    return c;
+}
+
+// cnt[0..nb] := 0 (a kernel, not a memset, so that graphs replay it)
+__global__ void clear_kernel(int *cnt, int n)
+{
+    if ((int)threadIdx.x < n)
+        cnt[threadIdx.x] = 0;
+}
+
+__global__ void count_kernel(CodeSet cs, const int32_t *code_of_frame,
+                             const int64_t *llr_off, const float *llr,
+                             int32_t B, int *cnt, int32_t *iters_out,
+                             int64_t *pe_out)
+{
+    for (int f = blockIdx.x * blockDim.x + threadIdx.x; f < B;
+         f += gridDim.x * blockDim.x) {
+        const int b = bucket_of(cs, code_of_frame, llr_off, llr, f);
+        if (b == cs.ncodes) {
+            iters_out[f] = 0;
+            if (pe_out)
+                pe_out[f] = 0;
+        }
+        atomicAdd(&cnt[b], 1);
+    }
+}
+
+// bounds[b] := start of bucket b (exclusive prefix of the counts), with
+// bounds[nb] = B; cursor[b] := bounds[b] for the scatter
+__global__ void scan_kernel(const int *cnt, int nb, int *bounds, int *cursor)
+{
+    if (threadIdx.x == 0) {
+        int s = 0;
+        for (int b = 0; b < nb; b++) {
+            bounds[b] = s;
+            cursor[b] = s;
+            s += cnt[b];
+        }
+        bounds[nb] = s;
+    }
+}
+
+__global__ void scatter_kernel(CodeSet cs, const int32_t *code_of_frame,
+                               const int64_t *llr_off, const float *llr,
+                               int32_t B, int *cursor, int32_t *order)
+{
+    for (int f = blockIdx.x * blockDim.x + threadIdx.x; f < B;
+         f += gridDim.x * blockDim.x) {
+        const int b = bucket_of(cs, code_of_frame, llr_off, llr, f);
+        order[atomicAdd(&cursor[b], 1)] = f;
+    }
+}
+
+// ---- tuner cache: (device, codes, mode) -> configuration ----
+
+using TuneKey = std::tuple<int, std::vector<std::pair<int, int>>, int, int>;
+
+std::mutex g_tune_mu;
+std::map<TuneKey, pbp_mixed_config> g_tune_cache;
+
+}  // namespace
+
+struct pbp_mixed_plan {
+    int device = 0;
+    int cus = 0;
+    int ncodes = 0;
+    int64_t max_frames = 0;
+    CodeDesc codes[kMaxCodes];
+    CodeSet cs{};
+    std::vector<std::pair<int, int>> dims;   // (N, K) per code
+    int *d_counters = nullptr;      // [head, waves out] per code
+    int *d_cnt = nullptr;           // ncodes + 1 bucket counts
+    int *d_bounds = nullptr;        // ncodes + 2 bucket bounds
+    int *d_cursor = nullptr;        // ncodes + 1 scatter cursors
+    int32_t *d_order = nullptr;     // max_frames
+    float *d_state = nullptr;       // slots of long codes
+    int64_t slot_floats = 0;
+    int64_t *d_stats = nullptr;     // 3 per wavefront per code
+    int last_waves[kMaxCodes] = {};
+    pbp_mixed_config cfg{1, 8};
+};
+
+namespace {
+
+struct Launch {
+    const void *kern;
+    size_t lds;
+};
+
+template <int M, int PATH>
+Launch launch_of()
+{
+    size_t lds = PATH >= 10 ? pbp::r10::smem_bytes()
+                            : pbp::generic::lds_bytes<M>(PATH);
+    return Launch{(const void *)class_kernel<M, PATH>, lds};
+}
+
+Launch class_launch(int m, int early_stop)
+{
+    switch (m) {
+    case 1: return launch_of<1, 0>();
+    case 2: return launch_of<2, 0>();
+    case 3: return launch_of<3, 0>();
+    case 4: return launch_of<4, 0>();
+    case 5: return launch_of<5, 0>();
+    case 6: return launch_of<6, 0>();
+    case 7: return launch_of<7, 0>();
+    case 8: return launch_of<8, 0>();
+    case 9: return launch_of<9, 0>();
+    case 10: return early_stop ? launch_of<10, 10>() : launch_of<10, 11>();
+    case 11: return launch_of<11, 2>();
+    case 12: return launch_of<12, 2>();
+    case 13: return launch_of<13, 2>();
+    case 14: return launch_of<14, 2>();
+    default: return Launch{nullptr, 0};
+    }
+}
+
+void free_plan(pbp_mixed_plan *p)
+{
+    if (!p)
+        return;
+    int prev = 0;
+    (void)hipGetDevice(&prev);
+    (void)hipSetDevice(p->device);
+    (void)hipDeviceSynchronize();
+    if (p->d_counters) (void)hipFree(p->d_counters);
+    if (p->d_cnt) (void)hipFree(p->d_cnt);
+    if (p->d_bounds) (void)hipFree(p->d_bounds);
+    if (p->d_cursor) (void)hipFree(p->d_cursor);
+    if (p->d_order) (void)hipFree(p->d_order);
+    if (p->d_state) (void)hipFree(p->d_state);
+    if (p->d_stats) (void)hipFree(p->d_stats);
+    (void)hipSetDevice(prev);
+    delete p;
+}
+
+bool valid_opts(const pbp_decode_opts *o)
+{
+    return o && o->max_iter >= 1 && (o->early_stop == 0 || o->early_stop == 1) &&
+           (o->freezing == 0 || o->freezing == 1) &&
+           (o->freeze_input == 0 || o->freeze_input == 1) &&
+           o->freeze_walk >= 0 && o->freeze_walk <= 2 && o->alpha > 0.0f &&
+           o->alpha < __builtin_inff();
+}
+
+bool valid_cfg(const pbp_mixed_config *c)
+{
+    return c && (c->order == 0 || c->order == 1) && c->waves_per_cu >= 1 &&
+           c->waves_per_cu <= kMaxWavesPerCu;
+}
+
+hipError_t enqueue(pbp_mixed_plan *p, const pbp_mixed_config &cfg,
+                   const int32_t *code_of_frame, const int64_t *llr_off,
+                   const int64_t *info_off, int32_t B, const float *llr,
+                   const pbp_decode_opts *o, uint8_t *info_out,
+                   int32_t *iters_out, int64_t *pe_out, hipStream_t st)
+{
+    const int nb = p->ncodes + 1;
+    const int g = (int)std::min<int64_t>((B + 255) / 256, 4096);
+    hipLaunchKernelGGL(clear_kernel, dim3(1), dim3(64), 0, st, p->d_cnt, nb);
+    hipLaunchKernelGGL(count_kernel, dim3(g), dim3(256), 0, st, p->cs,
+                       code_of_frame, llr_off, llr, B, p->d_cnt, iters_out,
+                       pe_out);
+    hipLaunchKernelGGL(scan_kernel, dim3(1), dim3(64), 0, st, p->d_cnt, nb,
+                       p->d_bounds, p->d_cursor);
+    hipLaunchKernelGGL(scatter_kernel, dim3(g), dim3(256), 0, st, p->cs,
+                       code_of_frame, llr_off, llr, B, p->d_cursor, p->d_order);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess)
+        return e;
+    // codes by decreasing (order 1) or increasing (order 0) length, stable
+    std::vector<int> seq(p->ncodes);
+    for (int c = 0; c < p->ncodes; c++)
+        seq[c] = c;
+    std::stable_sort(seq.begin(), seq.end(), [&](int a, int b) {
+        return cfg.order == 1 ? p->codes[a].m > p->codes[b].m
+                              : p->codes[a].m < p->codes[b].m;
+    });
+    int64_t grid = (int64_t)p->cus * cfg.waves_per_cu;
+    if (grid > B)
+        grid = B;
+    const int64_t max_waves = (int64_t)p->cus * kMaxWavesPerCu;
+    for (int c : seq) {
+        const Launch L = class_launch(p->codes[c].m, o->early_stop);
+        if (!L.kern)
+            return hipErrorInvalidValue;
+        ClassParams P{};
+        P.code = p->codes[c];
+        P.bounds = p->d_bounds;
+        P.bucket = c;
+        P.order = p->d_order;
+        P.llr_off = llr_off;
+        P.info_off = info_off;
+        P.llr = llr;
+        P.max_iter = o->max_iter;
+        P.early_stop = o->early_stop;
+        P.freezing = o->freezing;
+        P.freeze_input = o->freeze_input;
+        P.freeze_walk = o->freeze_walk;
+        P.alpha = o->alpha;
+        P.info_out = info_out;
+        P.iters_out = iters_out;
+        P.pe_out = pe_out;
+        P.counter = p->d_counters + 2 * c;
+        P.state = p->d_state;
+        P.slot_floats = p->slot_floats;
+        P.stats = p->d_stats + (int64_t)c * max_waves * 3;
+        p->last_waves[c] = (int)grid;
+        e = hipFuncSetAttribute(L.kern, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)L.lds);
+        if (e != hipSuccess)
+            return e;
+        void *args[] = {&P};
+        e = hipLaunchKernel(L.kern, dim3((unsigned)grid), dim3(64), args, L.lds,
+                            st);
+        if (e != hipSuccess)
+            return e;
+    }
+    return hipSuccess;
+}
+
+}  // namespace
+
+extern "C" int32_t pbp_mixed_plan_create(const pbp_code *const *codes,
+                                         int32_t ncodes, int64_t max_frames,
+                                         pbp_mixed_plan **out)
+{
+    if (!out)
+        return PBP_EINVAL;
+    *out = nullptr;
+    if (!codes || ncodes < 1 || ncodes > kMaxCodes || max_frames < 1 ||
+        max_frames > kMaxFrames)
+        return PBP_EINVAL;
+    for (int c = 0; c < ncodes; c++)
+        if (!codes[c] || codes[c]->device != codes[0]->device ||
+            codes[c]->m < 1 || codes[c]->m > 14)
+            return PBP_EINVAL;
+    pbp_mixed_plan *p = new (std::nothrow) pbp_mixed_plan();
+    if (!p)
+        return PBP_ENOMEM;
+    p->device = codes[0]->device;
+    p->cus = codes[0]->cus;
+    p->ncodes = ncodes;
+    p->max_frames = max_frames;
+    p->cs.ncodes = ncodes;
+    int max_long = 0;
+    for (int c = 0; c < ncodes; c++) {
+        const pbp_code *k = codes[c];
+        p->codes[c] = CodeDesc{k->m, k->K, k->d_frozen_words, k->d_info_pos,
+                               k->d_fzw10};
+        p->cs.m[c] = k->m;
+        p->dims.emplace_back(k->N, k->K);
+        if (k->m > pbp::r10::M)
+            max_long = std::max(max_long, k->m);
+    }
+    int prev = 0;
+    (void)hipGetDevice(&prev);
+    if (hipSetDevice(p->device) != hipSuccess) {
+        delete p;
+        return PBP_EDEVICE;
+    }
+    const int64_t waves = (int64_t)p->cus * kMaxWavesPerCu;
+    int32_t st = PBP_OK;
+    // codes longer than 1024 keep their message state (L and the working R
+    // column) in a slot per wavefront
+    if (max_long)
+        p->slot_floats = pbp::generic::slot_floats<14>(2) >> (14 - max_long);
+    if (hipMalloc(&p->d_counters, 2 * kMaxCodes * sizeof(int)) != hipSuccess ||
+        hipMalloc(&p->d_cnt, (kMaxCodes + 1) * sizeof(int)) != hipSuccess ||
+        hipMalloc(&p->d_bounds, (kMaxCodes + 2) * sizeof(int)) != hipSuccess ||
+        hipMalloc(&p->d_cursor, (kMaxCodes + 1) * sizeof(int)) != hipSuccess ||
+        hipMalloc(&p->d_order, max_frames * sizeof(int32_t)) != hipSuccess ||
+        hipMalloc(&p->d_stats, ncodes * waves * 3 * sizeof(int64_t)) != hipSuccess ||
+        (max_long && hipMalloc(&p->d_state, waves * p->slot_floats *
+                                                sizeof(float)) != hipSuccess))
+        st = PBP_ENOMEM;
+    else if (hipMemset(p->d_counters, 0, 2 * kMaxCodes * sizeof(int)) != hipSuccess ||
+             hipDeviceSynchronize() != hipSuccess)
+        st = PBP_EDEVICE;
+    (void)hipSetDevice(prev);
+    if (st != PBP_OK) {
+        free_plan(p);
+        return st;
+    }
+    *out = p;
+    return PBP_OK;
+}
+
+extern "C" void pbp_mixed_plan_destroy(pbp_mixed_plan *plan)
+{
+    free_plan(plan);
+}
+
+extern "C" int32_t pbp_mixed_plan_get_config(const pbp_mixed_plan *plan,
+                                             pbp_mixed_config *cfg)
+{
+    if (!plan || !cfg)
+        return PBP_EINVAL;
+    *cfg = plan->cfg;
+    return PBP_OK;
+}
+
+extern "C" int32_t pbp_mixed_plan_set_config(pbp_mixed_plan *plan,
+                                             const pbp_mixed_config *cfg)
+{
+    if (!plan || !valid_cfg(cfg))
+        return PBP_EINVAL;
+    plan->cfg = *cfg;
+    return PBP_OK;
+}
+
+extern "C" int32_t pbp_decode_mixed(pbp_mixed_plan *plan,
+                                    const int32_t *code_of_frame,
+                                    const int64_t *llr_off,
+                                    const int64_t *info_off, int64_t B,
+                                    const float *llr,
+                                    const pbp_decode_opts *opts,
+                                    uint8_t *info_out, int32_t *iters_out,
+                                    int64_t *pe_out, void *stream)
+{
+    if (!plan || B < 0 || B > plan->max_frames || !valid_opts(opts))
+        return PBP_EINVAL;
+    if (B == 0)
+        return PBP_OK;
+    if (!code_of_frame || !llr_off || !info_off || !llr || !info_out ||
+        !iters_out)
+        return PBP_EINVAL;
+    return enqueue(plan, plan->cfg, code_of_frame, llr_off, info_off,
+                   (int32_t)B, llr, opts, info_out, iters_out, pe_out,
+                   (hipStream_t)stream) == hipSuccess
+               ? PBP_OK
+               : PBP_EDEVICE;
+}
+
+extern "C" int32_t pbp_mixed_plan_fill(pbp_mixed_plan *plan, void *stream,
+                                       double *fill)
+{
+    if (!plan || !fill)
+        return PBP_EINVAL;
+    if (hipStreamSynchronize((hipStream_t)stream) != hipSuccess)
+        return PBP_EDEVICE;
+    const int64_t max_waves = (int64_t)plan->cus * kMaxWavesPerCu;
+    double busy = 0.0, span = 0.0;
+    for (int c = 0; c < plan->ncodes; c++) {
+        const int w = plan->last_waves[c];
+        if (w <= 0)
+            continue;
+        std::vector<int64_t> s((size_t)w * 3);
+        if (hipMemcpy(s.data(), plan->d_stats + (int64_t)c * max_waves * 3,
+                      s.size() * sizeof(int64_t),
+                      hipMemcpyDeviceToHost) != hipSuccess)
+            return PBP_EDEVICE;
+        int64_t t0 = s[0], t1 = s[1];
+        for (int i = 0; i < w; i++) {
+            t0 = std::min(t0, s[3 * i]);
+            t1 = std::max(t1, s[3 * i + 1]);
+            busy += (double)s[3 * i + 2];
+        }
+        span += (double)w * (double)(t1 - t0);
+    }
+    *fill = span > 0.0 ? busy / span : 0.0;
+    return PBP_OK;
+}
+
+extern "C" int32_t pbp_mixed_plan_tune(pbp_mixed_plan *plan,
+                                       const int32_t *code_of_frame,
+                                       const int64_t *llr_off,
+                                       const int64_t *info_off, int64_t B,
+                                       const float *llr,
+                                       const pbp_decode_opts *opts,
+                                       uint8_t *info_out, int32_t *iters_out,
+                                       int64_t *pe_out, int32_t reps,
+                                       void *stream, pbp_mixed_config *best)
+{
+    if (!plan || B < 1 || B > plan->max_frames || !valid_opts(opts) ||
+        reps < 1 || !code_of_frame || !llr_off || !info_off || !llr ||
+        !info_out || !iters_out)
+        return PBP_EINVAL;
+    TuneKey key{plan->device, plan->dims, opts->early_stop, opts->freezing};
+    {
+        std::lock_guard<std::mutex> g(g_tune_mu);
+        auto it = g_tune_cache.find(key);
+        if (it != g_tune_cache.end()) {
+            plan->cfg = it->second;
+            if (best)
+                *best = plan->cfg;
+            return PBP_OK;
+        }
+    }
+    hipStream_t st = (hipStream_t)stream;
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess)
+        return PBP_EDEVICE;
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return PBP_EDEVICE;
+    }
+    pbp_mixed_config cand[] = {{0, 2}, {0, 4}, {0, 6}, {0, 8},
+                               {1, 2}, {1, 4}, {1, 6}, {1, 8}};
+    float best_ms = 0.0f;
+    pbp_mixed_config best_cfg = plan->cfg;
+    int32_t status = PBP_OK;
+    for (const pbp_mixed_config &c : cand) {
+        // one untimed launch, then reps timed
+        if (enqueue(plan, c, code_of_frame, llr_off, info_off, (int32_t)B,
+                    llr, opts, info_out, iters_out, pe_out, st) != hipSuccess ||
+            hipEventRecord(e0, st) != hipSuccess) {
+            status = PBP_EDEVICE;
+            break;
+        }
+        bool ok = true;
+        for (int r = 0; r < reps && ok; r++)
+            ok = enqueue(plan, c, code_of_frame, llr_off, info_off, (int32_t)B,
+                         llr, opts, info_out, iters_out, pe_out, st) ==
+                 hipSuccess;
+        float ms = 0.0f;
+        if (!ok || hipEventRecord(e1, st) != hipSuccess ||
+            hipEventSynchronize(e1) != hipSuccess ||
+            hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+            status = PBP_EDEVICE;
+            break;
+        }
+        if (best_ms == 0.0f || ms < best_ms) {
+            best_ms = ms;
+            best_cfg = c;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (status != PBP_OK)
+        return status;
+    plan->cfg = best_cfg;
+    {
+        std::lock_guard<std::mutex> g(g_tune_mu);
+        g_tune_cache[key] = best_cfg;
+    }
+    if (best)
+        *best = best_cfg;
+    return PBP_OK;
+}

@@ -1,710 +1,14 @@
-// Register-resident BP decoder for N = 1024 (m = 10) on gfx950.
-//
-// One wavefront decodes one frame at a time; persistent wavefronts take
-// frames from a device counter.  Each lane owns 16 rows of the factor
-// graph.  Stages are taken in pairs (radix-4 groups); within a group the
-// butterflies of both stages are register-local because the two butterfly
-// row bits are register bits of that group's row-to-(register, lane)
-// mapping.  The other two register bits are always the top row bits 9 and
-// 8, so a frozen prefix of rows skips whole registers, uniformly over the
-// wavefront (the frozen prefixes of Section III are coarse: 256-row
-// granularity keeps most of the skipped PE work off the VALU).
-//
-//   mapping  register bits (q3 q2 q1 q0)   lane bits (l5..l0)   stages
-//   MA       9 8 1 0                        7 6 5 4 3 2          1 2 9 10
-//   MB       9 8 7 6                        5 4 3 2 1 0          3 4
-//   MC       9 8 5 4                        7 6 3 2 1 0          5 6
-//   MD       9 8 3 2                        7 6 5 4 1 0          7 8
-//
-// L columns written and read by the same group (2, 4, 6, 8, 10) and the
-// source prior (11) stay in VGPRs; the columns between groups (3, 5, 7, 9)
-// live in LDS; R crosses a group boundary through an LDS transpose.  The
-// hard decisions of the CSFG checks (eqs. (2)-(4)) and of the G-matrix stop
-// are ballot words (bit = lane) per register; the transform by F^{(x)s} is
-// word XORs along free register bits and shift/mask/XOR along free lane
-// bits, in scalar registers.  Stages 1 and 10 share mapping MA, so the stop
-// compares u G with the channel-side decisions without any reshuffle.
+// Batch kernel of the register-resident N = 1024 decoder: persistent
+// wavefronts take frames from a device counter (pbp_r10_decoder.h).
 #include <hip/hip_runtime.h>
 
 #include "pbp_internal.h"
 #include "pbp_r10.h"
+#include "pbp_r10_decoder.h"
 
 namespace pbp {
 namespace r10 {
 namespace {
-
-constexpr float kInf = __builtin_inff();
-
-__device__ __forceinline__ float gmin(float x, float y, float alpha)
-{
-    // sign(x) sign(y) min(|x|, |y|) is y, its sign flipped when x < 0,
-    // clamped to [-|x|, |x|]: one median of three (exact, a selection); the
-    // product with alpha then rounds once, symmetrically in sign
-    const float t = __uint_as_float(__float_as_uint(y) ^
-                                    (__float_as_uint(x) & 0x80000000u));
-    return alpha * __builtin_amdgcn_fmed3f(-fabsf(x), t, fabsf(x));
-}
-
-__device__ __forceinline__ void wave_sync()
-{
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
-// lanes whose lane-index bit b is set / clear
-__device__ constexpr uint64_t kLaneSet[6] = {
-    0xAAAAAAAAAAAAAAAAull, 0xCCCCCCCCCCCCCCCCull, 0xF0F0F0F0F0F0F0F0ull,
-    0xFF00FF00FF00FF00ull, 0xFFFF0000FFFF0000ull, 0xFFFFFFFF00000000ull};
-
-__device__ __forceinline__ uint64_t lane_clr(int b) { return ~kLaneSet[b]; }
-
-// butterfly of the lane-index bit b over a ballot word: lane i with bit b
-// clear takes bit i ^ bit (i + 2^b)
-__device__ __forceinline__ uint64_t ffx_lane(uint64_t w, int b)
-{
-    return w ^ ((w >> (1 << b)) & lane_clr(b));
-}
-
-__device__ __forceinline__ uint64_t ballot(bool p)
-{
-    return __ballot(p);
-}
-
-// The frozen ballot words are read-only for the whole launch: reading them
-// through the constant address space lets them come in by scalar loads.
-typedef const uint64_t __attribute__((address_space(4))) *const_u64_ptr;
-
-struct Params {
-    const float *llr;
-    int64_t B;
-    int *counter;
-    const uint64_t *fzw;   // [4][16] frozen ballot words per mapping
-    const int32_t *info_pos;
-    int32_t K;
-    int32_t max_iter, freezing, freeze_input, freeze_walk;
-    float alpha;
-    uint8_t *info_out;
-    int32_t *iters_out;
-    int64_t *pe_out;
-    float *soft_out;
-};
-
-// LDS per wavefront
-struct Smem {
-    float lb[4][N];      // L at columns 3, 5, 7, 9
-    float tb[N / 2];     // transpose buffer (half a frame at a time)
-    uint8_t dec[N];      // decided source bits of frozen rows
-};
-
-// Stage j: its mapping and the register bit of its butterfly.
-__host__ __device__ constexpr int smap(int j)
-{
-    return (j <= 2 || j >= 9) ? MA : (j <= 4 ? MB : (j <= 6 ? MC : MD));
-}
-__host__ __device__ constexpr int sqb(int j)
-{
-    return j == 1 ? 3 : j == 2 ? 2 : ((j & 1) ? 1 : 0);
-}
-// boundary LDS column index of L at column c (3, 5, 7, 9), else -1
-__host__ __device__ constexpr int lbcol(int c)
-{
-    return c == 3 ? 0 : c == 5 ? 1 : c == 7 ? 2 : c == 9 ? 3 : -1;
-}
-
-template <bool FRZ, bool ES>
-struct Decoder {
-    const Params &P;
-    Smem &S;
-    const int lane;
-    int lr[4];            // row bits contributed by this lane, per mapping
-    float ch[Q];          // channel LLRs (MA) for the next stage 1, reloaded
-                          // from device memory each iteration
-    float L2[Q], L4[Q], L6[Q], L8[Q], L10[Q];
-    float R[Q];
-    float Lt[Q];          // boundary column read for the current stage
-    uint64_t X[Q];        // channel-side hard decisions (MA ballot words)
-    int p[M + 1];         // frozen CSFG prefix length per stage
-    int l11lo, l11hi;     // rows that may be frozen at stage 10 and read
-    int walking;
-    int64_t pe;
-
-    // frozen ballot word [mapping mp][register q], by a scalar load at the
-    // point of use (the opaque base keeps it from being hoisted into long-lived
-    // scalar registers)
-    __device__ __forceinline__ uint64_t fz(int mp, int q) const
-    {
-        uint64_t base = reinterpret_cast<uint64_t>(P.fzw);
-        asm volatile("" : "+s"(base));
-        return reinterpret_cast<const_u64_ptr>(base)[mp * Q + q];
-    }
-
-    __device__ __forceinline__ Decoder(const Params &P_, Smem &S_, int lane_)
-        : P(P_), S(S_), lane(lane_)
-    {
-#pragma unroll
-        for (int mp = 0; mp < 4; mp++) {
-            int r = 0;
-#pragma unroll
-            for (int lb = 0; lb < 6; lb++)
-                if ((lane >> lb) & 1)
-                    r |= 1 << lrow(mp, lb);
-            lr[mp] = r;
-        }
-    }
-
-    template <int MP>
-    __device__ __forceinline__ int row(int q) const { return lr[MP] + rowq(MP, q); }
-
-    // largest row offset a lane contributes in mapping mp
-    static constexpr int lanemax(int mp)
-    {
-        int r = 0;
-        for (int lb = 0; lb < 6; lb++)
-            r |= 1 << lrow(mp, lb);
-        return r;
-    }
-
-    // L at column 11 (MA): +inf at frozen rows, 0 at information rows, and
-    // (-1)^u inf at rows frozen at stage 10 (single-row CSFGs, whose kept
-    // decision is u).  Only rows in [lo, hi) can be frozen at stage 10 and
-    // still be read, so only those consult the kept decisions.
-    __device__ __forceinline__ float l11(int q, int lo, int hi) const
-    {
-        const uint64_t fzq = fz(MA, q);
-        float v = ((fzq >> lane) & 1) ? kInf : 0.0f;
-        if (FRZ) {
-            const int rq = rowq(MA, q);
-            if (rq + 252 >= lo && rq < hi) {
-                const int r = row<MA>(q);
-                if (r >= lo && r < hi)
-                    v = S.dec[r] ? -kInf : kInf;
-            }
-        }
-        return v;
-    }
-
-    // register array holding L at column c in its group's mapping
-    template <int C>
-    __device__ __forceinline__ float *lreg()
-    {
-        if constexpr (C == 2) return L2;
-        else if constexpr (C == 4) return L4;
-        else if constexpr (C == 6) return L6;
-        else if constexpr (C == 8) return L8;
-        else if constexpr (C == 10) return L10;
-        else if constexpr (C == 3 || C == 5 || C == 7 || C == 9) return Lt;
-        else return nullptr;
-    }
-
-    // channel LLRs of a frame in mapping MA: register (qh, ql) of lane l is
-    // row 256 qh + 4 l + ql, so each lane reads four 16-byte vectors
-    __device__ __forceinline__ void load_channel(int64_t frame)
-    {
-        const float *src = P.llr + frame * N;
-#pragma unroll
-        for (int qh = 0; qh < 4; qh++) {
-            const float4 v = *reinterpret_cast<const float4 *>(src + qh * 256 + lane * 4);
-            ch[qh * 4 + 0] = v.x;
-            ch[qh * 4 + 1] = v.y;
-            ch[qh * 4 + 2] = v.z;
-            ch[qh * 4 + 3] = v.w;
-        }
-    }
-
-    __device__ __forceinline__ void load_frame(int64_t frame)
-    {
-        load_channel(frame);
-#pragma unroll
-        for (int q = 0; q < Q; q++)
-            L2[q] = L4[q] = L6[q] = L8[q] = L10[q] = 0.0f;
-#pragma unroll
-        for (int c = 0; c < 4; c++)
-#pragma unroll
-            for (int i = 0; i < N / 64; i++)
-                S.lb[c][i * 64 + lane] = 0.0f;
-#pragma unroll
-        for (int i = 0; i < N / 256; i++)
-            reinterpret_cast<uint32_t *>(S.dec)[i * 64 + lane] = 0u;
-#pragma unroll
-        for (int j = 0; j <= M; j++)
-            p[j] = 0;
-        pe = 0;
-        wave_sync();
-    }
-
-    // R crosses from mapping A to mapping B, half a frame (row bit 9) at a
-    // time through the transpose buffer.
-    template <int A, int Bm>
-    __device__ __forceinline__ void transpose_r()
-    {
-#pragma unroll
-        for (int h = 0; h < 2; h++) {
-#pragma unroll
-            for (int q = h * 8; q < h * 8 + 8; q++)
-                S.tb[row<A>(q) & (N / 2 - 1)] = R[q];
-            wave_sync();
-#pragma unroll
-            for (int q = h * 8; q < h * 8 + 8; q++)
-                R[q] = S.tb[row<Bm>(q) & (N / 2 - 1)];
-            wave_sync();
-        }
-    }
-
-    // One PE of eq. (1) on registers qa (row a) and qb = qa | BIT (row a + h).
-    // Lin = L at column J+1; the outputs L at column J go to registers, to
-    // LDS (boundary column) or into the channel-side decisions (J = 1).
-    template <int J, int QA>
-    __device__ __forceinline__ void pe_update()
-    {
-        constexpr int MP = smap(J);
-        constexpr int QB = QA | (1 << sqb(J));
-        const float alpha = P.alpha;
-        float La, Lb;
-        if constexpr (J == M) {
-            La = l11(QA, l11lo, l11hi);
-            Lb = l11(QB, l11lo, l11hi);
-        } else {
-            float *Lin = lreg<J + 1>();
-            La = Lin[QA];
-            Lb = Lin[QB];
-        }
-        const float Ra = (J == 1) ? ch[QA] : R[QA];
-        const float Rb = (J == 1) ? ch[QB] : R[QB];
-        const float s = Lb + Rb;
-        const float g1 = gmin(La, Ra, alpha);
-        const float la = gmin(La, s, alpha);
-        const float lbv = Lb + g1;
-        R[QA] = gmin(Ra, s, alpha);
-        R[QB] = Rb + g1;
-        if constexpr (J == 1) {
-            if constexpr (ES) {
-                X[QA] = ballot(Ra + la < 0.0f);
-                X[QB] = ballot(Rb + lbv < 0.0f);
-            }
-        } else if constexpr (lbcol(J) >= 0) {
-            S.lb[lbcol(J)][row<MP>(QA)] = la;
-            S.lb[lbcol(J)][row<MP>(QB)] = lbv;
-        } else {
-            float *Lout = lreg<J>();
-            Lout[QA] = la;
-            Lout[QB] = lbv;
-        }
-        // one PE at a time: dependent VALU operations issue back to back, so
-        // interleaving PEs buys nothing but register pressure
-        __builtin_amdgcn_sched_barrier(0);
-    }
-
-    // Register slots of a stage: PEs are grouped by the top two row bits of
-    // their upper row (register bits 3 and 2), except at stage 2, where the
-    // butterfly itself is on row bit 8 and the groups are the two halves.
-    template <int J>
-    static constexpr int slot_of(int qa) { return J == 2 ? (qa >> 3) * 2 : (qa >> 2); }
-
-    // PEs of stage J in register slot SLOT, all lanes active
-    template <int J, int QA, int SLOT>
-    __device__ __forceinline__ void pe_slot()
-    {
-        if constexpr (QA < Q) {
-            if constexpr (!((QA >> sqb(J)) & 1) && slot_of<J>(QA) == SLOT)
-                pe_update<J, QA>();
-            pe_slot<J, QA + 1, SLOT>();
-        }
-    }
-
-    // the same, each PE masked to the lanes whose row is >= f
-    template <int J, int QA, int SLOT>
-    __device__ __forceinline__ void pe_slot_masked(int f)
-    {
-        if constexpr (QA < Q) {
-            if constexpr (!((QA >> sqb(J)) & 1) && slot_of<J>(QA) == SLOT) {
-                constexpr int MP = smap(J);
-                if (lr[MP] + rowq(MP, QA) >= f)
-                    pe_update<J, QA>();
-            }
-            pe_slot_masked<J, QA + 1, SLOT>(f);
-        }
-    }
-
-    template <int J, int SLOT>
-    __device__ __forceinline__ void run_slot() { pe_slot<J, 0, SLOT>(); }
-
-    // Rows of slot s are [256 s, 256 s + 256).  Frozen prefix f: a slot
-    // entirely >= f runs unmasked, the slot holding f runs masked per lane,
-    // slots entirely below f are skipped.
-    template <int J, int SLOT>
-    __device__ __forceinline__ void slot_step(int f)
-    {
-        if (f <= SLOT * 256)
-            run_slot<J, SLOT>();
-        else if (f < SLOT * 256 + 256)
-            pe_slot_masked<J, 0, SLOT>(f);
-    }
-
-    template <int J>
-    __device__ __forceinline__ void stage_pes(int f)
-    {
-        if constexpr (J == 1 || !FRZ) {
-            run_slot<J, 0>(); run_slot<J, 1>(); run_slot<J, 2>(); run_slot<J, 3>();
-        } else {
-            slot_step<J, 0>(f);
-            slot_step<J, 1>(f);
-            slot_step<J, 2>(f);
-            slot_step<J, 3>(f);
-        }
-    }
-
-    template <int J>
-    __device__ __forceinline__ void stage(int f)
-    {
-        stage_pes<J>(f);
-        pe += (N - f) >> 1;
-    }
-
-    // the boundary column L at column J+1 (J even, J < 10) into Lt
-    template <int J>
-    __device__ __forceinline__ void load_lt()
-    {
-        constexpr int MP = smap(J);
-#pragma unroll
-        for (int q = 0; q < Q; q++)
-            Lt[q] = S.lb[lbcol(J + 1)][row<MP>(q)];
-    }
-
-    // ---- CSFG freezing walk at stage J (Section III, eqs. (2)-(4)) ----
-    //
-    // The block of CSFG k at stage J is the set of rows whose top J bits are
-    // k.  In the stage's mapping its rows are the registers whose fixed
-    // register bits (row bits >= 10 - J) match k, on the lanes whose fixed
-    // lane bits match k.  The register part is dispatched at compile time,
-    // so only the block's registers are touched.
-
-    template <int J>
-    static constexpr int fixed_qmask()
-    {
-        int fm = 0;
-        for (int qb = 0; qb < 4; qb++)
-            if (qrow(smap(J), qb) >= M - J)
-                fm |= 1 << qb;
-        return fm;
-    }
-
-    // value of register q's input to eq. (2)
-    template <int J>
-    __device__ __forceinline__ float check_input(int q)
-    {
-        if constexpr (J == M) {
-            return P.freeze_input ? R[q] + l11(q, 0, 0) : R[q];
-        } else {
-            const float *Ln = lreg<J + 1>();
-            return P.freeze_input ? R[q] + Ln[q] : R[q];
-        }
-    }
-
-    // check (and on success freeze) the block whose fixed register bits are
-    // T; lm selects the block's lanes.  Returns true when frozen.
-    template <int J, int T>
-    __device__ __forceinline__ bool check_block(uint64_t lm)
-    {
-        constexpr int MP = smap(J);
-        constexpr int SH = M - J;
-        constexpr int FM = fixed_qmask<J>();
-        constexpr int QL = T | (~FM & (Q - 1));    // all free register bits set
-        uint64_t W[Q];
-        // eq. (2) as ballot words; the transform of word QL needs no other
-        // word, so eqs. (3)-(4) are tested on it first
-        W[QL] = ballot(check_input<J>(QL) < 0.0f) & lm;
-        {
-            uint64_t w = W[QL];
-#pragma unroll
-            for (int lb = 0; lb < 6; lb++)
-                if (lrow(MP, lb) < SH)
-                    w = ffx_lane(w, lb);
-            if ((w & fz(MP, QL)) != 0)
-                return false;
-        }
-#pragma unroll
-        for (int q = 0; q < Q; q++)
-            if ((q & FM) == T && q != QL)
-                W[q] = ballot(check_input<J>(q) < 0.0f) & lm;
-        // eq. (3) along the free register bits
-#pragma unroll
-        for (int qb = 0; qb < 4; qb++)
-            if (!((FM >> qb) & 1))
-#pragma unroll
-                for (int q = 0; q < Q; q++)
-                    if ((q & FM) == T && !((q >> qb) & 1))
-                        W[q] ^= W[q | (1 << qb)];
-        // eq. (3) along the free lane bits and eq. (4), word by word
-        bool bad = false;
-#pragma unroll
-        for (int q = 0; q < Q; q++) {
-            if ((q & FM) == T && !bad) {
-                uint64_t w = W[q];
-#pragma unroll
-                for (int lb = 0; lb < 6; lb++)
-                    if (lrow(MP, lb) < SH)
-                        w = ffx_lane(w, lb);
-                W[q] = w;
-                bad = (w & fz(MP, q)) != 0;
-            }
-        }
-        if (bad)
-            return false;
-        // freeze: keep uhat; when L at column J+1 lives in LDS, fix it to
-        // (-1)^xhat inf there (register columns are fixed after the walk)
-        const bool mine = (lm >> lane) & 1;
-#pragma unroll
-        for (int q = 0; q < Q; q++) {
-            if ((q & FM) == T && mine) {
-                if constexpr (lbcol(J + 1) >= 0)
-                    S.lb[lbcol(J + 1)][row<MP>(q)] =
-                        check_input<J>(q) < 0.0f ? -kInf : kInf;
-                S.dec[row<MP>(q)] = (uint8_t)((W[q] >> lane) & 1);
-            }
-        }
-        wave_sync();
-        return true;
-    }
-
-    // L at column J+1 := (-1)^xhat inf on rows [lo, hi) when that column is
-    // held in registers (after the walk, so that the walk loop carries no
-    // register state)
-    template <int J>
-    __device__ __forceinline__ void fix_range(int lo, int hi)
-    {
-        constexpr int MP = smap(J);
-        if constexpr (lbcol(J + 1) < 0 && J < M) {
-            float *Ln = lreg<J + 1>();
-#pragma unroll
-            for (int q = 0; q < Q; q++) {
-                const int rq = rowq(MP, q);
-                if (rq + lanemax(MP) >= lo && rq < hi) {
-                    const int r = row<MP>(q);
-                    const float fixed = check_input<J>(q) < 0.0f ? -kInf : kInf;
-                    Ln[q] = (r >= lo && r < hi) ? fixed : Ln[q];
-                }
-            }
-        }
-    }
-
-    // binary dispatch over the fixed-register-bit values T in [LO, HI)
-    template <int J, int LO, int HI>
-    __device__ __forceinline__ bool dispatch(int t, uint64_t lm)
-    {
-        constexpr int FM = fixed_qmask<J>();
-        if constexpr (HI - LO == 1) {
-            if constexpr ((LO & FM) == LO)
-                return check_block<J, LO>(lm);
-            else
-                return false;
-        } else {
-            constexpr int MID = (LO + HI) / 2;
-            if (t < MID)
-                return dispatch<J, LO, MID>(t, lm);
-            return dispatch<J, MID, HI>(t, lm);
-        }
-    }
-
-    // check CSFG k of stage J (and freeze it on success)
-    template <int J>
-    __device__ __forceinline__ bool check_k(int k)
-    {
-        constexpr int MP = smap(J);
-        constexpr int SH = M - J;          // row bits below SH are free
-        constexpr int FM = fixed_qmask<J>();
-        // lanes inside block k
-        uint64_t lm = ~0ull;
-#pragma unroll
-        for (int lb = 0; lb < 6; lb++) {
-            const int rb = lrow(MP, lb);
-            if (rb >= SH)
-                lm &= ((k >> (rb - SH)) & 1) ? kLaneSet[lb] : lane_clr(lb);
-        }
-        // fixed register bits of block k
-        int t = 0;
-#pragma unroll
-        for (int qb = 0; qb < 4; qb++)
-            if ((FM >> qb) & 1)
-                t |= ((k >> (qrow(MP, qb) - SH)) & 1) << qb;
-        return dispatch<J, 0, 16>(t, lm);
-    }
-
-    template <int J>
-    __device__ __forceinline__ void freeze_walk()
-    {
-        constexpr int SH = M - J;
-        if (!P.freezing)
-            return;
-        int pj = max(p[J], 2 * p[J - 1]);
-        const int k0 = pj;
-        // At most one freeze per stage unless the walk is greedy; the common
-        // path is loop-free so that no check input is hoisted out of a loop.
-        if (pj < (1 << J) && (P.freeze_walk != 0 || walking)) {
-            if (check_k<J>(pj)) {
-                pj++;
-                if (P.freeze_walk == 0)
-                    walking = 0;
-                if (P.freeze_walk == 2)
-                    while (pj < (1 << J) && check_k<J>(pj))
-                        pj++;
-            }
-        }
-        if (pj > k0)
-            fix_range<J>(k0 << SH, pj << SH);
-        p[J] = pj;
-    }
-
-    template <int J>
-    __device__ __forceinline__ void step()
-    {
-        int f = 0;
-        if constexpr (FRZ)
-            f = p[J - 1] << (M - J + 1);
-        if constexpr (J == M) {
-            l11lo = f;                       // rows below f are not read
-            l11hi = FRZ ? p[M] : 0;          // rows frozen at stage 10 so far
-        }
-        // keep each stage's LDS reads inside the stage (hoisting them ahead
-        // only lengthens register lifetimes)
-        asm volatile("" ::: "memory");
-        if constexpr ((J & 1) == 0 && J < M)
-            load_lt<J>();
-        stage<J>(f);
-        if constexpr (FRZ)
-            freeze_walk<J>();
-    }
-
-    // source-word decisions of register q (MA) as a ballot word: the hard
-    // decision of R at column 11, 0 at frozen rows, and the kept CSFG
-    // decisions on rows below the frozen prefix fm
-    __device__ __forceinline__ uint64_t u_word(int q, int fm)
-    {
-        uint64_t u = ballot(R[q] < 0.0f) & ~fz(MA, q);
-        if (FRZ) {
-            const int base = rowq(MA, q);         // lane l holds row base + 4l
-            if (fm > base) {
-                const uint64_t d = ballot(S.dec[row<MA>(q)] != 0);
-                if (fm > base + 252) {
-                    u = d;
-                } else {
-                    const int T = (fm - base + 3) >> 2;   // lanes below fm
-                    const uint64_t pm = (1ull << T) - 1;
-                    u = (u & ~pm) | (d & pm);
-                }
-            }
-        }
-        return u;
-    }
-
-    // decisions at column 11 and the stop test; returns true to stop
-    __device__ __forceinline__ bool decide()
-    {
-        const int fm = FRZ ? p[M] : 0;
-        if (FRZ && fm == N)
-            return true;
-        if constexpr (!ES)
-            return false;
-        // G-matrix test: u F^{(x)10} == xhat.  Output word 15 (all register
-        // bits set) depends on input word 15 alone: test it first.
-        {
-            uint64_t w = u_word(Q - 1, fm);
-#pragma unroll
-            for (int lb = 0; lb < 6; lb++)
-                w = ffx_lane(w, lb);
-            if (w != X[Q - 1])
-                return false;
-        }
-        uint64_t U[Q];
-#pragma unroll
-        for (int q = 0; q < Q; q++)
-            U[q] = u_word(q, fm);
-#pragma unroll
-        for (int qb = 0; qb < 4; qb++)
-#pragma unroll
-            for (int q = 0; q < Q; q++)
-                if (!((q >> qb) & 1))
-                    U[q] ^= U[q | (1 << qb)];
-        bool same = true;
-#pragma unroll
-        for (int q = 0; q < Q - 1; q++) {
-            if (same) {
-                uint64_t w = U[q];
-#pragma unroll
-                for (int lb = 0; lb < 6; lb++)
-                    w = ffx_lane(w, lb);
-                same = w == X[q];
-            }
-        }
-        return same;
-    }
-
-    __device__ __forceinline__ void write_outputs(int64_t frame, int iters)
-    {
-        const int fm = FRZ ? p[M] : 0;
-        // source-word decisions of the non-frozen rows into the LDS table
-#pragma unroll
-        for (int q = 0; q < Q; q++) {
-            const int r = row<MA>(q);
-            if (r >= fm)
-                S.dec[r] = (uint8_t)(R[q] < 0.0f);
-        }
-        wave_sync();
-        uint8_t *out = P.info_out + frame * P.K;
-        for (int k = lane; k < P.K; k += 64)
-            out[k] = S.dec[P.info_pos[k]];
-        if (P.soft_out) {
-            float *so = P.soft_out + frame * N;
-#pragma unroll
-            for (int qh = 0; qh < 4; qh++) {
-                float v[4];
-#pragma unroll
-                for (int ql = 0; ql < 4; ql++) {
-                    const int q = qh * 4 + ql;
-                    const int r = row<MA>(q);
-                    v[ql] = r < fm ? (S.dec[r] ? -kInf : kInf) : R[q] + l11(q, 0, 0);
-                }
-                *reinterpret_cast<float4 *>(so + qh * 256 + lane * 4) =
-                    make_float4(v[0], v[1], v[2], v[3]);
-            }
-        }
-        if (lane == 0) {
-            P.iters_out[frame] = iters;
-            if (P.pe_out)
-                P.pe_out[frame] = pe;
-        }
-        wave_sync();
-    }
-
-    __device__ __forceinline__ void decode(int64_t frame)
-    {
-        load_frame(frame);
-        int t = 1;
-        for (; t <= P.max_iter; t++) {
-            walking = 1;
-            step<1>();
-            step<2>();
-            transpose_r<MA, MB>();
-            step<3>();
-            step<4>();
-            transpose_r<MB, MC>();
-            step<5>();
-            step<6>();
-            transpose_r<MC, MD>();
-            step<7>();
-            step<8>();
-            transpose_r<MD, MA>();
-            load_channel(frame);        // for the next iteration's stage 1
-            step<9>();
-            step<10>();
-            if (decide())
-                break;
-        }
-        if (t > P.max_iter)
-            t = P.max_iter;
-        write_outputs(frame, t);
-    }
-};
 
 template <bool FRZ, bool ES>
 __global__ __launch_bounds__(64, 2) void bp_decode_r10_kernel(Params P)
