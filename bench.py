@@ -171,11 +171,19 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--batch", type=int, default=1 << 16)
-    ap.add_argument("--ebn0", type=float, default=3.0)
+    ap.add_argument("--batch", type=int, default=0,
+                    help="frames per step (0: the workload's default)")
+    ap.add_argument("--ebn0", type=float, default=None,
+                    help="Eb/N0 in dB (default: the workload's)")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-reference-modes", action="store_true")
+    ap.add_argument("--workload", default="n1024",
+                    choices=["n1024", "n16384", "mixed", "unrolled"],
+                    help="n1024: the headline line (default); n16384: the "
+                         "long-code decoder; mixed: the mixed-code persistent "
+                         "decoder; unrolled: one training step of the "
+                         "unrolled decoder")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run a plain device copy of BYTES (counter "
                          "yardstick) and exit")
@@ -192,11 +200,18 @@ def main():
     if args.copy_calibration:
         copy_calibration(torch, args.copy_calibration, max(1, args.steps))
         return
+    if args.workload != "n1024":
+        fn = {"n16384": bench_long_code, "mixed": bench_mixed,
+              "unrolled": bench_unrolled}[args.workload]
+        print(json.dumps(fn(args, pbp, torch)), flush=True)
+        return
 
-    N, K, B, max_iter, alpha = 1024, 512, args.batch, 40, 0.9375
+    N, K, B, max_iter, alpha = 1024, 512, args.batch or (1 << 16), 40, 0.9375
     frozen = pbp.pbp_construct(N, K, 0.0)
     code = pbp.Code(N, K, frozen)
     t0 = time.perf_counter()
+    if args.ebn0 is None:
+        args.ebn0 = 3.0
     info, d_llr = make_inputs(pbp, torch, code, frozen, N, K, B, args.ebn0,
                               stream=(2 << 16) + 5)
     gen_s = time.perf_counter() - t0
@@ -263,6 +278,226 @@ def main():
                                             args.cpu_seconds)
     line["input_generation_s"] = round(gen_s, 2)
     print(json.dumps(line), flush=True)
+
+
+# ---------------------------------------------------------------------------
+# Other workloads (one JSON line each; not the headline)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def _line(metric, value, unit, steps, warmup, ms, config, **extra):
+    d = {"metric": metric, "value": value, "unit": unit, "n_gpus": 1,
+         "steps": steps, "warmup": warmup, "ms_per_step": round(ms, 4),
+         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+         "dtype": "f32", "data": "synthetic", "config": config}
+    d.update(extra)
+    return d
+
+
+def _timed(torch, fn, steps, warmup):
+    fn()
+    torch.cuda.synchronize()
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    for _ in range(steps):
+        fn()
+    ev1.record()
+    torch.cuda.synchronize()
+    return ev0.elapsed_time(ev1) / steps
+
+
+def bench_long_code(args, pbp, torch):
+    """(16384, 8192) code at 2.0 dB, early stop + freezing, 60 iterations:
+    the message state of each frame lives in device memory, so the decoder
+    is bound by HBM traffic (16 B per active PE: two L messages read, two
+    written; plus the channel LLRs once per iteration)."""
+    N, K, max_iter, alpha = 16384, 8192, 60, 0.9375
+    ebn0 = 2.0 if args.ebn0 is None else args.ebn0
+    B = args.batch or 4096
+    frozen = pbp.pbp_construct(N, K, 0.0)
+    code = pbp.Code(N, K, frozen)
+    info, d_llr = make_inputs(pbp, torch, code, frozen, N, K, B, ebn0,
+                              stream=(5 << 16) + 1)
+    opts = dict(MODES["es_frz"], max_iter=max_iter, alpha=alpha)
+    out = pbp.pbp_decode(code, d_llr, **opts)
+    steps = max(1, args.steps // 2)
+    ms = _timed(torch, lambda: pbp.pbp_decode(code, d_llr, out=out, **opts),
+                steps, 1)
+    iters = out["iters"].cpu().numpy().astype(np.float64)
+    pe = out["pe"].cpu().numpy().astype(np.float64)
+    errs = int(np.sum(np.any(out["info"].cpu().numpy() != info, axis=1)))
+    alg_bytes = 16.0 * pe.sum() + 4.0 * N * iters.sum() + B * (K + 12)
+    gbs = alg_bytes / (ms / 1e3) / 1e9
+    ops = OPS_PER_PE * pe.sum() / (ms / 1e3) / 1e12
+    return _line(
+        "decoded info Mbit/s, N=16384 R=1/2 2.0dB", round(B * K / ms / 1e3, 2),
+        "Mbit/s", steps, 1, ms,
+        {"workload": "polar BP decode, (16384,8192) code, BPSK/AWGN Eb/N0 "
+                     f"{ebn0} dB, early stop + CSFG freezing, max 60 "
+                     "iterations, message state in device memory",
+         "N": N, "K": K, "ebn0_db": ebn0, "frames_per_step": B,
+         "max_iter": max_iter},
+        avg_iters=round(float(iters.mean()), 3),
+        pe_per_frame=round(float(pe.mean()), 1), fer=errs / B,
+        roofline={"bound": "hbm", "achieved": round(gbs, 1),
+                  "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                  "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None,
+                  "kernel": "bp_decode_kernel<14, true>",
+                  "kernel_ms": round(ms, 4)},
+        valu={"achieved": round(ops, 3), "peak": round(VALU_PEAK_TOPS, 3),
+              "unit": "TOP/s", "frac": round(ops / VALU_PEAK_TOPS, 4)})
+
+
+def bench_mixed(args, pbp, torch):
+    """2^20 frames mixing N in {256, 1024, 4096} and R in {1/3, 1/2, 5/6}
+    uniformly, Eb/N0 uniform in [1, 4] dB per frame, early stop + freezing,
+    60 iterations, one mixed-code decode per step (autotuned first)."""
+    import synth
+    dims = [(n, int(n * r)) for n in (256, 1024, 4096)
+            for r in (1 / 3, 1 / 2, 5 / 6)]
+    B = args.batch or (1 << 20)
+    stream = (3 << 16) + 1
+    t0 = time.perf_counter()
+    u = synth.uniform(B, stream=stream, word=0)
+    cof = np.minimum((u * len(dims)).astype(np.int32), len(dims) - 1)
+    ebn0 = 1.0 + 3.0 * synth.uniform(B, stream=stream, word=1)
+    Ns = np.array([dims[c][0] for c in cof], np.int64)
+    Ks = np.array([dims[c][1] for c in cof], np.int64)
+    llr_off = np.concatenate([[0], np.cumsum(Ns)[:-1]]).astype(np.int64)
+    info_off = np.concatenate([[0], np.cumsum(Ks)[:-1]]).astype(np.int64)
+    d_llr = torch.empty(int(Ns.sum()), dtype=torch.float32, device="cuda")
+    codes = []
+    info_ref = {}
+    for c, (N, K) in enumerate(dims):
+        frozen = pbp.pbp_construct(N, K, 0.0)
+        code = pbp.Code(N, K, frozen)
+        codes.append(code)
+        idx = np.flatnonzero(cof == c)
+        info = synth.info_bits(K, len(idx), stream=stream * 16 + c + 1)
+        info_ref[c] = (idx, info)
+        cw = pbp.pbp_encode(code, torch.from_numpy(info).cuda()).cpu().numpy()
+        # channel LLRs in chunks (bounded host memory), scattered to the
+        # frames' offsets on the device
+        for lo in range(0, len(idx), 16384):
+            sl = slice(lo, lo + 16384)
+            nz = synth.normals(N, len(idx[sl]), frame0=lo,
+                               stream=stream * 16 + c + 1)
+            llr = torch.from_numpy(synth.channel_llr(
+                cw[sl], nz, ebn0[idx[sl]], K / N)).cuda()
+            pos = torch.from_numpy(llr_off[idx[sl]]).cuda()[:, None] + \
+                torch.arange(N, device="cuda")[None, :]
+            d_llr[pos.reshape(-1)] = llr.reshape(-1)
+    gen_s = time.perf_counter() - t0
+    d = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    d_cof, d_lo, d_io = d(cof), d(llr_off), d(info_off)
+    plan = pbp.MixedPlan(codes, B)
+    opts = pbp.make_opts(max_iter=60, **MODES["es_frz"])
+    nbits = int(Ks.sum())
+    out = {"info": torch.empty(nbits, dtype=torch.uint8, device="cuda"),
+           "iters": torch.empty(B, dtype=torch.int32, device="cuda"),
+           "pe": torch.empty(B, dtype=torch.int64, device="cuda")}
+    t1 = time.perf_counter()
+    cfg = pbp.pbp_mixed_plan_tune(plan, d_cof, d_lo, d_io, d_llr, opts=opts,
+                                  out=out, reps=1)
+    tune_s = time.perf_counter() - t1
+    steps = max(1, args.steps // 3)
+    ms = _timed(torch, lambda: pbp.pbp_decode_mixed(
+        plan, d_cof, d_lo, d_io, d_llr, opts=opts, out=out), steps, 1)
+    fill = pbp.pbp_mixed_plan_fill(plan)
+    pe = out["pe"].cpu().numpy().astype(np.float64)
+    iters = out["iters"].cpu().numpy()
+    bits = out["info"].cpu().numpy()
+    errs = 0
+    for c, (idx, info) in info_ref.items():
+        K = dims[c][1]
+        got = bits[info_off[idx][:, None] + np.arange(K)[None, :]]
+        errs += int(np.sum(np.any(got != info, axis=1)))
+    ops = OPS_PER_PE * pe.sum() / (ms / 1e3) / 1e12
+    return _line(
+        "decoded info Mbit/s, mixed N in {256,1024,4096} x R in "
+        "{1/3,1/2,5/6}, Eb/N0 U[1,4] dB", round(nbits / ms / 1e3, 2),
+        "Mbit/s", steps, 1, ms,
+        {"workload": "mixed-code persistent decode, 2^20 frames, (N, R) "
+                     "uniform over 9 codes, early stop + CSFG freezing, max "
+                     "60 iterations", "frames_per_step": B,
+         "codes": [list(x) for x in dims]},
+        frames_per_s=round(B / ms * 1e3, 1), fill_efficiency=round(fill, 4),
+        tuned_config={"order": cfg[0], "waves_per_cu": cfg[1]},
+        avg_iters=round(float(iters.mean()), 3),
+        pe_per_frame=round(float(pe.mean()), 1), fer=errs / B,
+        roofline={"bound": "alu", "achieved": round(ops, 3),
+                  "peak": round(VALU_PEAK_TOPS, 3), "unit": "TOP/s",
+                  "frac": round(ops / VALU_PEAK_TOPS, 4), "traffic": None,
+                  "kernel": "class_kernel<M, PATH> (one per code)",
+                  "kernel_ms": round(ms, 4)},
+        input_generation_s=round(gen_s, 2), tune_s=round(tune_s, 2))
+
+
+def bench_unrolled(args, pbp, torch):
+    """One training step of the unrolled decoder: (1024, 512) code, T = 20,
+    4096 frames at Eb/N0 uniform in [1, 4] dB: forward with checkpoints,
+    BCE of the information bits, backward to the 400 scales."""
+    import synth
+    N, K, T = 1024, 512, 20
+    m = 10
+    B = args.batch or 4096
+    stream = (4 << 16) + 1
+    frozen = pbp.pbp_construct(N, K, 0.0)
+    code = pbp.Code(N, K, frozen)
+    ebn0 = 1.0 + 3.0 * synth.uniform(B, stream=stream, word=1)
+    info = synth.info_bits(K, B, stream=stream)
+    cw = pbp.pbp_encode(code, torch.from_numpy(info).cuda()).cpu().numpy()
+    llr = synth.channel_llr(cw, synth.normals(N, B, stream=stream), ebn0,
+                            K / N)
+    d_llr = torch.from_numpy(llr).cuda()
+    info_pos = torch.from_numpy(np.flatnonzero(frozen == 0)).cuda()
+    u_info = torch.from_numpy(info.astype(np.float32)).cuda()
+    alpha = torch.full((T, m, 2), 0.9375, dtype=torch.float32, device="cuda",
+                       requires_grad=True)
+    opt = torch.optim.SGD([alpha], lr=0.01)
+
+    def step():
+        opt.zero_grad(set_to_none=False)
+        loss = pbp.info_bce(pbp.unrolled_bp(d_llr, alpha, code), u_info,
+                            info_pos)
+        loss.backward()
+        opt.step()
+
+    steps = max(1, args.steps)
+    ms = _timed(torch, step, steps, 2)
+    # forward and backward kernels alone
+    a = alpha.detach().clone()
+    ck = torch.empty((T, B, m - 1, N), dtype=torch.float32, device="cuda")
+    o = torch.empty((B, N), dtype=torch.float32, device="cuda")
+    fwd_ms = _timed(torch, lambda: pbp.pbp_unrolled_forward(
+        code, d_llr, a, ckpt=ck, out=o), steps, 1)
+    dout = torch.randn((B, N), device="cuda")
+    bwd_ms = _timed(torch, lambda: pbp.pbp_unrolled_backward(
+        code, d_llr, a, ck, dout), steps, 1)
+    ck_bytes = 4.0 * T * B * (m - 1) * N
+    fwd_gbs = (ck_bytes + 8.0 * B * N) / (fwd_ms / 1e3) / 1e9
+    pe = float(T) * m * N / 2 * B
+    return _line(
+        "unrolled BP training step, frames/s (N=1024, T=20)",
+        round(B / ms * 1e3, 1), "frames/s", steps, 2, ms,
+        {"workload": "unrolled BP training step, (1024,512) code, T=20, "
+                     "400 scales, 4096 frames, Eb/N0 U[1,4] dB",
+         "N": N, "K": K, "T": T, "frames_per_step": B},
+        forward_ms=round(fwd_ms, 4), backward_ms=round(bwd_ms, 4),
+        roofline={"bound": "hbm", "achieved": round(fwd_gbs, 1),
+                  "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                  "frac": round(fwd_gbs / HBM_PEAK_GBS, 4), "traffic": None,
+                  "kernel": "unrolled_forward_kernel<10>",
+                  "kernel_ms": round(fwd_ms, 4),
+                  "note": "checkpoint writes (T x B x (m-1) x N x 4 B) plus "
+                          "LLR reads and output writes"},
+        valu_forward={"achieved": round(OPS_PER_PE * pe / (fwd_ms / 1e3) / 1e12, 3),
+                      "peak": round(VALU_PEAK_TOPS, 3), "unit": "TOP/s"})
 
 
 if __name__ == "__main__":
