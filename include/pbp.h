@@ -152,8 +152,9 @@ typedef struct {
 
 /* Create a plan for up to max_frames frames (1 .. 2^30) over ncodes code
  * handles (1..16, all on one device; they must outlive the plan).  Device
- * memory: the queue (4 B per frame) and, when a code has N >= 1024, one
- * message slot per wavefront ((m+2) 2^m floats for the longest such code).
+ * memory: the queue (4 B per frame) and, when a code has N >= 2048, one
+ * message slot per resident workgroup ((m+1) 2^m floats for the longest
+ * such code, 2 workgroups per compute unit).
  * Default configuration: {1, 8}.  Errors: PBP_EINVAL, PBP_ENOMEM,
  * PBP_EDEVICE. */
 int32_t pbp_mixed_plan_create(const pbp_code *const *codes, int32_t ncodes,

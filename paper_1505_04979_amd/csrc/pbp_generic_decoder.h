@@ -6,8 +6,9 @@
 // stage by stage (stage j reads R at column j and writes R at column j+1 on
 // the same rows), the channel LLRs in a second column, and the
 // right-to-left messages L at columns 1..m+1.  Placement (STATE): 0 = all in
-// LDS; 1 = L in a device-memory slot, the two R columns in LDS; 2 = L and
-// the working R column in the slot, channel LLRs read in place.  Hard
+// LDS; 1 = L in a device-memory slot, the working R column in LDS, channel
+// LLRs read in place; 2 = L and the working R column in the slot, channel
+// LLRs read in place.  Hard
 // decisions are packed 64 to a word with wavefront ballots; the transform by
 // F^{(x)s} runs on those words (shift/mask/xor inside a word, xor across
 // words by cross-lane shuffles).  The CSFG walk and the stop test run on
@@ -138,13 +139,14 @@ __device__ __forceinline__ void sync()
 }
 
 // LDS bytes of one decoder instance: [u64 xw NW][u64 dw NW][Ctl], then
-// [f32 Rw N][f32 ch N] unless STATE == 2, then L (m+1 columns) if STATE == 0
+// [f32 Rw N] unless STATE == 2, then [f32 ch N] and L (m+1 columns) if
+// STATE == 0
 template <int M>
 __host__ __device__ constexpr size_t lds_bytes(int state)
 {
     return 2 * sizeof(uint64_t) * Layout<M>::NW + sizeof(Ctl) +
-           (state < 2 ? 2 * sizeof(float) * (1u << M) : 0) +
-           (state == 0 ? sizeof(float) * (size_t)(M + 1) * (1u << M) : 0);
+           (state < 2 ? sizeof(float) * (1u << M) : 0) +
+           (state == 0 ? sizeof(float) * (size_t)(M + 2) * (1u << M) : 0);
 }
 
 // floats of a device-memory slot: L (m+1 columns), plus the working R
@@ -185,10 +187,10 @@ __device__ __forceinline__ void decode_frame(const DecodeParams &P,
     asm volatile("" : "+s"(NT));
 
     const float *llr = P.llr + frame * N;
-    const float *ch = STATE == 2 ? llr : chl;
+    const float *ch = STATE != 0 ? llr : chl;
     // ---- initial messages ----
     for (int i = tid; i < N; i += NT) {
-        if (STATE != 2)
+        if (STATE == 0)
             chl[i] = llr[i];
         for (int c = 1; c <= M; c++)
             Lc(c)[i] = 0.0f;
@@ -216,6 +218,7 @@ __device__ __forceinline__ void decode_frame(const DecodeParams &P,
             float *Lj = Lc(j);
             const float *Lj1 = Lc(j + 1);
             // ---- PE updates, eq. (1) ----
+#pragma unroll 4
             for (int q = (f >> 1) + tid; q < N / 2; q += NT) {
                 const int a = ((q >> s) << (s + 1)) | (q & (h - 1));
                 const int b = a + h;

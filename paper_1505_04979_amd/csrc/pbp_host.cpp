@@ -174,8 +174,13 @@ extern "C" int32_t pbp_code_create(int32_t N, int32_t K, const uint8_t *frozen,
     }
     if (c->m > pbp::kMaxLdsLog) {
         // message state of codes too long for LDS: one slot per resident
-        // workgroup, (m + 1) columns of N floats each
-        c->state_slots = (int64_t)c->cus * 2;
+        // workgroup, (m + 1) columns of N floats each.  The workgroups hold
+        // the working R column and two bit words per 64 rows in LDS, so as
+        // many as fit in 160 KB (at most 4) are resident per compute unit.
+        const int64_t lds = 4 * (int64_t)N + 16 * (int64_t)(N / 64) + 128;
+        int64_t per_cu = (160 * 1024) / lds;
+        per_cu = per_cu < 1 ? 1 : (per_cu > 4 ? 4 : per_cu);
+        c->state_slots = (int64_t)c->cus * per_cu;
         c->state_floats_per_slot = (int64_t)(c->m + 1) * N;
         if (hipMalloc(&c->d_state, sizeof(float) * c->state_slots *
                                        c->state_floats_per_slot) != hipSuccess) {

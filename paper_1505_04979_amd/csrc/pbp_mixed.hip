@@ -5,12 +5,12 @@
 // code).  Each code's segment is then drained by its own persistent kernel,
 // specialised for that code length: a pool of wavefronts, each taking the
 // next queue entry from a device counter, reading the frame's buffer
-// offsets and decoding the whole frame alone -- N = 1024 with the
+// offsets and decoding the whole frame -- N = 1024 with the
 // register-resident decoder, N <= 512 with the generic decoder and its state
-// in the wavefront's LDS, N >= 2048 with the generic decoder and its state in
-// the wavefront's device-memory slot.  The last wavefront out of a kernel
-// rewinds its counter, so the enqueued work needs no host-side or memset
-// reset and can be captured in a graph and replayed.
+// in the wavefront's LDS, and N >= 2048 with the generic decoder run by a
+// 256-thread workgroup that keeps L in its device-memory slot.  The last
+// group out of a kernel rewinds its counter, so the enqueued work needs no
+// host-side or memset reset and can be captured in a graph and replayed.
 //
 // Configuration: the order in which the code segments are drained (longest
 // code first or shortest first) and the number of resident wavefronts per
@@ -68,16 +68,15 @@ struct ClassParams {
 using pbp::generic::DecodeParams;
 using pbp::generic::decode_frame;
 
-// PATH: 0 = generic decoder, state in LDS; 2 = generic decoder, state in a
-// device slot; 10 = register decoder with early stop; 11 = register decoder
-// without early stop (freezing switched at run time)
+// One wavefront per frame.  PATH: 0 = generic decoder, state in LDS;
+// 10 = register decoder with early stop; 11 = register decoder without early
+// stop (freezing switched at run time)
 template <int M, int PATH>
 __global__ __launch_bounds__(64, 2) void class_kernel(ClassParams P)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     const int lane = (int)__builtin_amdgcn_workitem_id_x();
     const int64_t wave = blockIdx.x;
-    float *gslot = PATH == 2 ? P.state + wave * P.slot_floats : nullptr;
     const int lo = P.bounds[P.bucket], hi = P.bounds[P.bucket + 1];
     const int64_t t_start = wall_clock64();
     int64_t busy = 0;
@@ -128,7 +127,7 @@ __global__ __launch_bounds__(64, 2) void class_kernel(ClassParams P)
             D.iters_out = P.iters_out + f;
             D.pe_out = P.pe_out ? P.pe_out + f : nullptr;
             D.soft_out = nullptr;
-            decode_frame<M, PATH, true>(D, 0, smem, gslot, lane, 64);
+            decode_frame<M, PATH, true>(D, 0, smem, nullptr, lane, 64);
         }
         busy += wall_clock64() - t0;
     }
@@ -138,6 +137,61 @@ __global__ __launch_bounds__(64, 2) void class_kernel(ClassParams P)
         P.stats[wave * 3 + 2] = busy;
         // every wavefront has taken its last queue entry before it counts
         // itself out; the last one out rewinds both counters
+        if (atomicAdd(P.counter + 1, 1) == (int)gridDim.x - 1) {
+            atomicExch(P.counter, 0);
+            atomicExch(P.counter + 1, 0);
+        }
+    }
+}
+
+// Long codes: a 256-thread workgroup decodes each frame (L in the
+// workgroup's device slot, the working R column in LDS).
+constexpr int kWgThreads = 256;
+
+template <int M>
+__global__ __launch_bounds__(kWgThreads) void class_wg_kernel(ClassParams P)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ int s_q;
+    const int tid = (int)threadIdx.x;
+    const int64_t wg = blockIdx.x;
+    float *gslot = P.state + wg * P.slot_floats;
+    const int lo = P.bounds[P.bucket], hi = P.bounds[P.bucket + 1];
+    const int64_t t_start = wall_clock64();
+    int64_t busy = 0;
+    for (;;) {
+        if (tid == 0)
+            s_q = atomicAdd(P.counter, 1) + lo;
+        __syncthreads();
+        const int q = s_q;
+        __syncthreads();
+        if (q >= hi)
+            break;
+        const int64_t t0 = wall_clock64();
+        const int f = P.order[q];
+        DecodeParams D{};
+        D.llr = P.llr + P.llr_off[f];
+        D.B = 1;
+        D.frozen_words = P.code.frozen_words;
+        D.info_pos = P.code.info_pos;
+        D.K = P.code.K;
+        D.max_iter = P.max_iter;
+        D.early_stop = P.early_stop;
+        D.freezing = P.freezing;
+        D.freeze_input = P.freeze_input;
+        D.freeze_walk = P.freeze_walk;
+        D.alpha = P.alpha;
+        D.info_out = P.info_out + P.info_off[f];
+        D.iters_out = P.iters_out + f;
+        D.pe_out = P.pe_out ? P.pe_out + f : nullptr;
+        D.soft_out = nullptr;
+        decode_frame<M, 1, false>(D, 0, smem, gslot, tid, kWgThreads);
+        busy += wall_clock64() - t0;
+    }
+    if (tid == 0) {
+        P.stats[wg * 3] = t_start;
+        P.stats[wg * 3 + 1] = wall_clock64();
+        P.stats[wg * 3 + 2] = busy;
         if (atomicAdd(P.counter + 1, 1) == (int)gridDim.x - 1) {
             atomicExch(P.counter, 0);
             atomicExch(P.counter + 1, 0);
@@ -252,14 +306,20 @@ namespace {
 struct Launch {
     const void *kern;
     size_t lds;
+    int threads;
 };
 
 template <int M, int PATH>
 Launch launch_of()
 {
-    size_t lds = PATH >= 10 ? pbp::r10::smem_bytes()
-                            : pbp::generic::lds_bytes<M>(PATH);
-    return Launch{(const void *)class_kernel<M, PATH>, lds};
+    if constexpr (PATH == 1) {
+        return Launch{(const void *)class_wg_kernel<M>,
+                      pbp::generic::lds_bytes<M>(1), kWgThreads};
+    } else {
+        size_t lds = PATH >= 10 ? pbp::r10::smem_bytes()
+                                : pbp::generic::lds_bytes<M>(PATH);
+        return Launch{(const void *)class_kernel<M, PATH>, lds, 64};
+    }
 }
 
 Launch class_launch(int m, int early_stop)
@@ -275,10 +335,10 @@ Launch class_launch(int m, int early_stop)
     case 8: return launch_of<8, 0>();
     case 9: return launch_of<9, 0>();
     case 10: return early_stop ? launch_of<10, 10>() : launch_of<10, 11>();
-    case 11: return launch_of<11, 2>();
-    case 12: return launch_of<12, 2>();
-    case 13: return launch_of<13, 2>();
-    case 14: return launch_of<14, 2>();
+    case 11: return launch_of<11, 1>();
+    case 12: return launch_of<12, 1>();
+    case 13: return launch_of<13, 1>();
+    case 14: return launch_of<14, 1>();
     default: return Launch{nullptr, 0};
     }
 }
@@ -344,14 +404,16 @@ hipError_t enqueue(pbp_mixed_plan *p, const pbp_mixed_config &cfg,
         return cfg.order == 1 ? p->codes[a].m > p->codes[b].m
                               : p->codes[a].m < p->codes[b].m;
     });
-    int64_t grid = (int64_t)p->cus * cfg.waves_per_cu;
-    if (grid > B)
-        grid = B;
     const int64_t max_waves = (int64_t)p->cus * kMaxWavesPerCu;
     for (int c : seq) {
         const Launch L = class_launch(p->codes[c].m, o->early_stop);
         if (!L.kern)
             return hipErrorInvalidValue;
+        // resident groups: waves_per_cu wavefronts per compute unit in all
+        int64_t grid = (int64_t)p->cus *
+                       std::max(1, cfg.waves_per_cu * 64 / L.threads);
+        if (grid > B)
+            grid = B;
         ClassParams P{};
         P.code = p->codes[c];
         P.bounds = p->d_bounds;
@@ -379,8 +441,8 @@ hipError_t enqueue(pbp_mixed_plan *p, const pbp_mixed_config &cfg,
         if (e != hipSuccess)
             return e;
         void *args[] = {&P};
-        e = hipLaunchKernel(L.kern, dim3((unsigned)grid), dim3(64), args, L.lds,
-                            st);
+        e = hipLaunchKernel(L.kern, dim3((unsigned)grid), dim3(L.threads), args,
+                            L.lds, st);
         if (e != hipSuccess)
             return e;
     }
@@ -428,18 +490,18 @@ extern "C" int32_t pbp_mixed_plan_create(const pbp_code *const *codes,
         return PBP_EDEVICE;
     }
     const int64_t waves = (int64_t)p->cus * kMaxWavesPerCu;
+    const int64_t groups = waves * 64 / kWgThreads;   // long-code workgroups
     int32_t st = PBP_OK;
-    // codes longer than 1024 keep their message state (L and the working R
-    // column) in a slot per wavefront
+    // codes longer than 1024 keep L in a slot per resident workgroup
     if (max_long)
-        p->slot_floats = pbp::generic::slot_floats<14>(2) >> (14 - max_long);
+        p->slot_floats = (int64_t)(max_long + 1) << max_long;
     if (hipMalloc(&p->d_counters, 2 * kMaxCodes * sizeof(int)) != hipSuccess ||
         hipMalloc(&p->d_cnt, (kMaxCodes + 1) * sizeof(int)) != hipSuccess ||
         hipMalloc(&p->d_bounds, (kMaxCodes + 2) * sizeof(int)) != hipSuccess ||
         hipMalloc(&p->d_cursor, (kMaxCodes + 1) * sizeof(int)) != hipSuccess ||
         hipMalloc(&p->d_order, max_frames * sizeof(int32_t)) != hipSuccess ||
         hipMalloc(&p->d_stats, ncodes * waves * 3 * sizeof(int64_t)) != hipSuccess ||
-        (max_long && hipMalloc(&p->d_state, waves * p->slot_floats *
+        (max_long && hipMalloc(&p->d_state, groups * p->slot_floats *
                                                 sizeof(float)) != hipSuccess))
         st = PBP_ENOMEM;
     else if (hipMemset(p->d_counters, 0, 2 * kMaxCodes * sizeof(int)) != hipSuccess ||

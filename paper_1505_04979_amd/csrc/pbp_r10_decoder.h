@@ -416,6 +416,9 @@ struct Decoder {
         constexpr int FM = fixed_qmask<J>();
         constexpr int QL = T | (~FM & (Q - 1));    // all free register bits set
         uint64_t W[Q];
+        // the frozen word is requested first, so that its load overlaps the
+        // ballot and the transform
+        const uint64_t fzl = fz(MP, QL);
         // eq. (2) as ballot words; the transform of word QL needs no other
         // word, so eqs. (3)-(4) are tested on it first
         W[QL] = ballot(check_input<J>(QL) < 0.0f) & lm;
@@ -425,7 +428,7 @@ struct Decoder {
             for (int lb = 0; lb < 6; lb++)
                 if (lrow(MP, lb) < SH)
                     w = ffx_lane(w, lb);
-            if ((w & fz(MP, QL)) != 0)
+            if ((w & fzl) != 0)
                 return false;
         }
 #pragma unroll
@@ -585,7 +588,8 @@ struct Decoder {
     // decisions on rows below the frozen prefix fm
     __device__ __forceinline__ uint64_t u_word(int q, int fm)
     {
-        uint64_t u = ballot(R[q] < 0.0f) & ~fz(MA, q);
+        const uint64_t fzq = fz(MA, q);
+        uint64_t u = ballot(R[q] < 0.0f) & ~fzq;
         if (FRZ) {
             const int base = rowq(MA, q);         // lane l holds row base + 4l
             if (fm > base) {
