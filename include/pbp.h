@@ -120,7 +120,7 @@ int32_t pbp_encode(const pbp_code *code, const uint8_t *info, int64_t B,
  *   soft_out  device, B x N FP32, or NULL: the posterior LLR of each source
  *             bit at exit (R + L at column m+1; +-inf inside frozen CSFGs)
  * A handle holds per-call device state (the frame counter of the persistent
- * kernels, the message state of codes longer than 2048): calls on one handle
+ * kernels, the message state of codes longer than 1024): calls on one handle
  * must be ordered on one stream, never in flight on two streams at once.
  * Errors: PBP_EINVAL (bad options, B < 0, NULL required pointer),
  * PBP_EDEVICE (launch failure). */
@@ -143,8 +143,10 @@ typedef struct pbp_mixed_plan pbp_mixed_plan;
 /* Launch configuration.
  *  order         0: the queue takes frames in the caller's order;
  *                1: longest code first (a counting sort on the device)
- *  waves_per_cu  resident wavefronts per compute unit, 1..8 (each wavefront
- *                decodes one frame at a time) */
+ *  waves_per_cu  resident one-wavefront groups per compute unit, 1..8
+ *                (each decodes one frame at a time); codes with N >= 2048
+ *                are decoded by 256-thread groups, waves_per_cu / 2 of them
+ *                (at least 1) per compute unit */
 typedef struct {
     int32_t order;
     int32_t waves_per_cu;
@@ -154,7 +156,7 @@ typedef struct {
  * handles (1..16, all on one device; they must outlive the plan).  Device
  * memory: the queue (4 B per frame) and, when a code has N >= 2048, one
  * message slot per resident workgroup ((m+1) 2^m floats for the longest
- * such code, 2 workgroups per compute unit).
+ * such code, 4 workgroups per compute unit).
  * Default configuration: {1, 8}.  Errors: PBP_EINVAL, PBP_ENOMEM,
  * PBP_EDEVICE. */
 int32_t pbp_mixed_plan_create(const pbp_code *const *codes, int32_t ncodes,

@@ -2,7 +2,7 @@
 //
 // Batch decoder: one workgroup decodes one frame at a time (grid-stride over
 // the batch) with the generic decoder of pbp_generic_decoder.h, its message
-// state in LDS (N <= 2048) or in a per-workgroup slot of device memory
+// state in LDS (N <= 1024) or in a per-workgroup slot of device memory
 // (larger N).  N = 1024 goes to the register-resident decoder instead.
 #include <hip/hip_runtime.h>
 

@@ -70,6 +70,11 @@ __device__ __forceinline__ void wave_sync()
 // Up to 4 words per lane: blocks of at most 16384 bits.
 constexpr int kMaxWordsPerLane = 4;
 
+// Words whose input loads are issued together before their ballots (with L
+// in device memory, one dependent load per word would serialise the walk
+// and the stop test on memory latency).
+constexpr int kBatch = 8;
+
 // In-register F^{(x)s} transform of nw words (nw a power of two, word w =
 // lane + 64 q held in r[q]); each word already transformed internally.
 __device__ __forceinline__ void ffx_cross(uint64_t (&r)[kMaxWordsPerLane],
@@ -218,7 +223,7 @@ __device__ __forceinline__ void decode_frame(const DecodeParams &P,
             float *Lj = Lc(j);
             const float *Lj1 = Lc(j + 1);
             // ---- PE updates, eq. (1) ----
-#pragma unroll 4
+#pragma unroll 8
             for (int q = (f >> 1) + tid; q < N / 2; q += NT) {
                 const int a = ((q >> s) << (s + 1)) | (q & (h - 1));
                 const int b = a + h;
@@ -243,19 +248,25 @@ __device__ __forceinline__ void decode_frame(const DecodeParams &P,
                 const int nw = h >= 64 ? h >> 6 : 1;
                 while (pj < (1 << j) && (P.freeze_walk != 0 || walking)) {
                     const int r0 = pj << s;
-                    // eq. (2): hard decisions of the CSFG's inputs
-                    for (int w = 0; w < nw; w++) {
-                        const int i = 64 * w + lane;
-                        bool x = false;
-                        if (i < h) {
-                            const float v = P.freeze_input
-                                                ? Rw[r0 + i] + L1[r0 + i]
-                                                : Rw[r0 + i];
-                            x = v < 0.0f;
+                    // eq. (2): hard decisions of the CSFG's inputs, the
+                    // loads of kBatch words in flight before their ballots
+#pragma unroll 1
+                    for (int w0 = 0; w0 < nw; w0 += kBatch) {
+                        float v[kBatch];
+#pragma unroll
+                        for (int u = 0; u < kBatch; u++) {
+                            const int i = 64 * (w0 + u) + lane;
+                            v[u] = 0.0f;
+                            if (w0 + u < nw && i < h)
+                                v[u] = P.freeze_input ? Rw[r0 + i] + L1[r0 + i]
+                                                      : Rw[r0 + i];
                         }
-                        const uint64_t bal = __ballot(x);
-                        if (lane == 0)
-                            xw[w] = bal;
+#pragma unroll
+                        for (int u = 0; u < kBatch; u++) {
+                            const uint64_t bal = __ballot(v[u] < 0.0f);
+                            if (lane == 0 && w0 + u < nw)
+                                xw[w0 + u] = bal;
+                        }
                     }
                     sync<true>();
                     // eq. (3): uhat = xhat F^{(x)s}
@@ -332,18 +343,29 @@ __device__ __forceinline__ void decode_frame(const DecodeParams &P,
                 // column 1
                 const float *L1 = Lc(1);
                 uint64_t r[kMaxWordsPerLane];
-                for (int w = 0; w < NW; w++) {
-                    const int i = 64 * w + lane;
-                    bool u = false;
-                    if (i < N) {
-                        if (i < fm)
-                            u = (dw[i >> 6] >> (i & 63)) & 1;
-                        else
-                            u = !frozen_bit(P.frozen_words, i) && Rw[i] < 0.0f;
+#pragma unroll 1
+                for (int w0 = 0; w0 < NW; w0 += kBatch) {
+                    float rv[kBatch];
+#pragma unroll
+                    for (int u = 0; u < kBatch; u++) {
+                        const int i = 64 * (w0 + u) + lane;
+                        rv[u] = (w0 + u < NW && i < N) ? Rw[i] : 0.0f;
                     }
-                    const uint64_t bal = __ballot(u);
-                    if (lane == 0)
-                        xw[w] = bal;
+#pragma unroll
+                    for (int u = 0; u < kBatch; u++) {
+                        const int w = w0 + u;
+                        const int i = 64 * w + lane;
+                        bool x = false;
+                        if (w < NW && i < N) {
+                            if (i < fm)
+                                x = (dw[w] >> (i & 63)) & 1;
+                            else
+                                x = !frozen_bit(P.frozen_words, i) && rv[u] < 0.0f;
+                        }
+                        const uint64_t bal = __ballot(x);
+                        if (lane == 0 && w < NW)
+                            xw[w] = bal;
+                    }
                 }
                 sync<true>();
 #pragma unroll
@@ -353,18 +375,27 @@ __device__ __forceinline__ void decode_frame(const DecodeParams &P,
                 }
                 ffx_cross(r, NW, lane);
                 bool diff = false;
-                for (int w = 0; w < NW; w++) {
-                    const int i = 64 * w + lane;
-                    const bool x = i < N && (ch[i] + L1[i] < 0.0f);
-                    const uint64_t bal = __ballot(x);
-                    // the lane holding word w compares it
-                    if ((w & 63) == lane) {
-                        const int q = w >> 6;
-                        uint64_t mine = r[0];
-                        if (q == 1) mine = r[1];
-                        if (q == 2) mine = r[2];
-                        if (q == 3) mine = r[3];
-                        diff |= mine != bal;
+#pragma unroll 1
+                for (int w0 = 0; w0 < NW; w0 += kBatch) {
+                    float v[kBatch];
+#pragma unroll
+                    for (int u = 0; u < kBatch; u++) {
+                        const int i = 64 * (w0 + u) + lane;
+                        v[u] = (w0 + u < NW && i < N) ? ch[i] + L1[i] : 0.0f;
+                    }
+#pragma unroll
+                    for (int u = 0; u < kBatch; u++) {
+                        const int w = w0 + u;
+                        const uint64_t bal = __ballot(v[u] < 0.0f);
+                        // the lane holding word w compares it
+                        if (w < NW && (w & 63) == lane) {
+                            const int q = w >> 6;
+                            uint64_t mine = r[0];
+                            if (q == 1) mine = r[1];
+                            if (q == 2) mine = r[2];
+                            if (q == 3) mine = r[3];
+                            diff |= mine != bal;
+                        }
                     }
                 }
                 stop = !__any(diff);

@@ -42,6 +42,6 @@ inline int log2i(int32_t N)
 }
 
 // Largest code length whose full message state lives in LDS.
-constexpr int kMaxLdsLog = 11;
+constexpr int kMaxLdsLog = 10;
 
 }  // namespace pbp

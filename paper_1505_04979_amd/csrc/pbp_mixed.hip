@@ -409,9 +409,12 @@ hipError_t enqueue(pbp_mixed_plan *p, const pbp_mixed_config &cfg,
         const Launch L = class_launch(p->codes[c].m, o->early_stop);
         if (!L.kern)
             return hipErrorInvalidValue;
-        // resident groups: waves_per_cu wavefronts per compute unit in all
+        // resident groups per compute unit: waves_per_cu one-wavefront
+        // groups, or half as many 256-thread groups (their wavefronts wait
+        // on memory, so twice the wavefronts are resident)
         int64_t grid = (int64_t)p->cus *
-                       std::max(1, cfg.waves_per_cu * 64 / L.threads);
+                       (L.threads == 64 ? cfg.waves_per_cu
+                                        : std::max(1, cfg.waves_per_cu / 2));
         if (grid > B)
             grid = B;
         ClassParams P{};
@@ -490,7 +493,7 @@ extern "C" int32_t pbp_mixed_plan_create(const pbp_code *const *codes,
         return PBP_EDEVICE;
     }
     const int64_t waves = (int64_t)p->cus * kMaxWavesPerCu;
-    const int64_t groups = waves * 64 / kWgThreads;   // long-code workgroups
+    const int64_t groups = waves / 2;                 // long-code workgroups
     int32_t st = PBP_OK;
     // codes longer than 1024 keep L in a slot per resident workgroup
     if (max_long)
