@@ -481,6 +481,10 @@ def bench_unrolled(args, pbp, torch):
         code, d_llr, a, ck, dout), steps, 1)
     ck_bytes = 4.0 * T * B * (m - 1) * N
     fwd_gbs = (ck_bytes + 8.0 * B * N) / (fwd_ms / 1e3) / 1e9
+    # backward: checkpoints read once, LLRs and output gradients read,
+    # channel gradients and per-frame scale gradients written
+    bwd_bytes = ck_bytes + 12.0 * B * N + 4.0 * B * T * m * 2
+    bwd_gbs = bwd_bytes / (bwd_ms / 1e3) / 1e9
     pe = float(T) * m * N / 2 * B
     return _line(
         "unrolled BP training step, frames/s (N=1024, T=20)",
@@ -489,13 +493,17 @@ def bench_unrolled(args, pbp, torch):
                      "400 scales, 4096 frames, Eb/N0 U[1,4] dB",
          "N": N, "K": K, "T": T, "frames_per_step": B},
         forward_ms=round(fwd_ms, 4), backward_ms=round(bwd_ms, 4),
-        roofline={"bound": "hbm", "achieved": round(fwd_gbs, 1),
+        roofline={"bound": "hbm", "achieved": round(bwd_gbs, 1),
                   "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                  "frac": round(fwd_gbs / HBM_PEAK_GBS, 4), "traffic": None,
-                  "kernel": "unrolled_forward_kernel<10>",
-                  "kernel_ms": round(fwd_ms, 4),
-                  "note": "checkpoint writes (T x B x (m-1) x N x 4 B) plus "
-                          "LLR reads and output writes"},
+                  "frac": round(bwd_gbs / HBM_PEAK_GBS, 4), "traffic": None,
+                  "kernel": "unrolled_backward_kernel<10>",
+                  "kernel_ms": round(bwd_ms, 4),
+                  "note": "checkpoint reads (T x B x (m-1) x N x 4 B), LLR "
+                          "and output-gradient reads, gradient writes"},
+        forward_roofline={"bound": "hbm", "achieved": round(fwd_gbs, 1),
+                          "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                          "frac": round(fwd_gbs / HBM_PEAK_GBS, 4),
+                          "kernel": "unrolled_forward_kernel<10>"},
         valu_forward={"achieved": round(OPS_PER_PE * pe / (fwd_ms / 1e3) / 1e12, 3),
                       "peak": round(VALU_PEAK_TOPS, 3), "unit": "TOP/s"})
 

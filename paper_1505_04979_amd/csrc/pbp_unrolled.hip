@@ -59,6 +59,16 @@ __device__ __forceinline__ void g0_back(float x, float y, float d, float &dx,
     dy += cy;
 }
 
+// The scales are read-only for the whole launch: reading them through the
+// constant address space makes them scalar loads, which do not wait behind
+// the vector loads in flight.
+typedef const float __attribute__((address_space(4))) *const_f32_ptr;
+
+__device__ __forceinline__ float scale_at(const float *alpha, int64_t i)
+{
+    return reinterpret_cast<const_f32_ptr>(reinterpret_cast<uintptr_t>(alpha))[i];
+}
+
 __device__ __forceinline__ bool frozen_at(const uint64_t *fw, int i)
 {
     return (fw[i >> 6] >> (i & 63)) & 1;
@@ -70,6 +80,9 @@ struct Shape {
     static constexpr int H = N / 2;                 // PEs per stage
     static constexpr int NT = H < 64 ? 64 : H;      // threads per workgroup
     static constexpr int NW = NT / 64;              // wavefronts
+    static constexpr int YR = (N + NT - 1) / NT;    // LLRs per thread
+    // checkpoint floats per thread (L at columns 2..m)
+    static constexpr int CR = M > 1 ? ((M - 1) * N + NT - 1) / NT : 1;
 };
 
 struct FwdParams {
@@ -119,7 +132,13 @@ __global__ __launch_bounds__(Shape<M>::NT) void unrolled_forward_kernel(FwdParam
     const int tid = (int)threadIdx.x;
 
     for (int64_t f = blockIdx.x; f < P.B; f += gridDim.x) {
-        const float *y = P.llr + f * N;
+        // the frame's LLRs stay in registers for all T iterations
+        float yv[S::YR];
+#pragma unroll
+        for (int k = 0; k < S::YR; k++) {
+            const int i = tid + k * NT;
+            yv[k] = i < N ? P.llr[f * N + i] : 0.0f;
+        }
         for (int i = tid; i < N; i += NT) {
             for (int c = 0; c < M - 1; c++)
                 L[c * N + i] = 0.0f;
@@ -132,12 +151,16 @@ __global__ __launch_bounds__(Shape<M>::NT) void unrolled_forward_kernel(FwdParam
                 for (int i = tid; i < (M - 1) * N; i += NT)
                     ck[i] = L[i];
             }
-            for (int i = tid; i < N; i += NT)
-                R[i] = y[i];
+#pragma unroll
+            for (int k = 0; k < S::YR; k++) {
+                const int i = tid + k * NT;
+                if (i < N)
+                    R[i] = yv[k];
+            }
             __syncthreads();
             for (int j = 1; j <= M; j++) {
-                const float aL = P.alpha[((int64_t)t * M + (j - 1)) * 2];
-                const float aR = P.alpha[((int64_t)t * M + (j - 1)) * 2 + 1];
+                const float aL = scale_at(P.alpha, ((int64_t)t * M + (j - 1)) * 2);
+                const float aR = scale_at(P.alpha, ((int64_t)t * M + (j - 1)) * 2 + 1);
                 const int sh = M - j, h = 1 << sh;
                 if (tid < H) {
                     const int a = ((tid >> sh) << (sh + 1)) | (tid & (h - 1));
@@ -166,6 +189,20 @@ __global__ __launch_bounds__(Shape<M>::NT) void unrolled_forward_kernel(FwdParam
     }
 }
 
+// this thread's share of the checkpoint of iteration t of frame f
+template <int M>
+__device__ __forceinline__ void load_ckpt(const BwdParams &P, int t, int64_t f,
+                                          int tid, float (&cv)[Shape<M>::CR])
+{
+    using S = Shape<M>;
+    const float *ck = P.ckpt + ((int64_t)t * P.B + f) * (M - 1) * S::N;
+#pragma unroll
+    for (int k = 0; k < S::CR; k++) {
+        const int i = tid + k * S::NT;
+        cv[k] = i < (M - 1) * S::N ? ck[i] : 0.0f;
+    }
+}
+
 template <int M>
 __global__ __launch_bounds__(Shape<M>::NT) void unrolled_backward_kernel(BwdParams P)
 {
@@ -182,7 +219,17 @@ __global__ __launch_bounds__(Shape<M>::NT) void unrolled_backward_kernel(BwdPara
     const int lane = tid & 63, wv = tid >> 6;
 
     for (int64_t f = blockIdx.x; f < P.B; f += gridDim.x) {
-        const float *y = P.llr + f * N;
+        // the frame's LLRs stay in registers; the checkpoint of the next
+        // iteration (in reverse order) is loaded into registers while the
+        // current one is processed
+        float yv[S::YR], dv[S::YR], cv[S::CR];
+#pragma unroll
+        for (int k = 0; k < S::YR; k++) {
+            const int i = tid + k * NT;
+            yv[k] = i < N ? P.llr[f * N + i] : 0.0f;
+            dv[k] = i < N ? P.dout[f * N + i] : 0.0f;
+        }
+        load_ckpt<M>(P, P.T - 1, f, tid, cv);
         for (int i = tid; i < N; i += NT) {
             Lp[(M - 1) * N + i] = frozen_at(P.frozen, i) ? kInf : 0.0f;
             for (int c = 0; c < M - 1; c++)
@@ -190,15 +237,24 @@ __global__ __launch_bounds__(Shape<M>::NT) void unrolled_backward_kernel(BwdPara
             dC[i] = 0.0f;
         }
         for (int t = P.T - 1; t >= 0; t--) {
-            const float *ck = P.ckpt + ((int64_t)t * P.B + f) * (M - 1) * N;
-            for (int i = tid; i < (M - 1) * N; i += NT)
-                Lp[i] = ck[i];
-            for (int i = tid; i < N; i += NT)
-                Rc[i] = y[i];
+#pragma unroll
+            for (int k = 0; k < S::CR; k++) {
+                const int i = tid + k * NT;
+                if (i < (M - 1) * N)
+                    Lp[i] = cv[k];
+            }
+#pragma unroll
+            for (int k = 0; k < S::YR; k++) {
+                const int i = tid + k * NT;
+                if (i < N)
+                    Rc[i] = yv[k];
+            }
+            if (t > 0)
+                load_ckpt<M>(P, t - 1, f, tid, cv);
             __syncthreads();
             // the R sweep of iteration t+1
             for (int j = 1; j <= M; j++) {
-                const float aR = P.alpha[((int64_t)t * M + (j - 1)) * 2 + 1];
+                const float aR = scale_at(P.alpha, ((int64_t)t * M + (j - 1)) * 2 + 1);
                 const int sh = M - j, h = 1 << sh;
                 if (tid < H) {
                     const int a = ((tid >> sh) << (sh + 1)) | (tid & (h - 1));
@@ -216,13 +272,17 @@ __global__ __launch_bounds__(Shape<M>::NT) void unrolled_backward_kernel(BwdPara
             }
             {
                 float *d = dR + ((M + 1) & 1) * N;
-                for (int i = tid; i < N; i += NT)
-                    d[i] = t == P.T - 1 ? P.dout[f * N + i] : 0.0f;
+#pragma unroll
+                for (int k = 0; k < S::YR; k++) {
+                    const int i = tid + k * NT;
+                    if (i < N)
+                        d[i] = t == P.T - 1 ? dv[k] : 0.0f;
+                }
             }
             __syncthreads();
             for (int j = M; j >= 1; j--) {
-                const float aL = P.alpha[((int64_t)t * M + (j - 1)) * 2];
-                const float aR = P.alpha[((int64_t)t * M + (j - 1)) * 2 + 1];
+                const float aL = scale_at(P.alpha, ((int64_t)t * M + (j - 1)) * 2);
+                const float aR = scale_at(P.alpha, ((int64_t)t * M + (j - 1)) * 2 + 1);
                 const int sh = M - j, h = 1 << sh;
                 float daL = 0.0f, daR = 0.0f;
                 if (tid < H) {
