@@ -133,15 +133,33 @@ struct Decoder {
     int l11lo, l11hi;     // rows that may be frozen at stage 10 and read
     int walking;
     int64_t pe;
+    // frozen mask as per-lane bits: bit 16 (mp & 1) + q of fzb[mp >> 1] says
+    // whether the row of register q in mapping mp is frozen on this lane
+    // (two registers, so the checks need no scalar loads and their waits)
+    uint32_t fzb[2];
 
-    // frozen ballot word [mapping mp][register q], by a scalar load at the
-    // point of use (the opaque base keeps it from being hoisted into long-lived
-    // scalar registers)
-    __device__ __forceinline__ uint64_t fz(int mp, int q) const
+    // frozen ballot word [mapping mp][register q] as stored by the host
+    __device__ __forceinline__ uint64_t fz_word(int mp, int q) const
     {
         uint64_t base = reinterpret_cast<uint64_t>(P.fzw);
         asm volatile("" : "+s"(base));
         return reinterpret_cast<const_u64_ptr>(base)[mp * Q + q];
+    }
+
+    // this lane's frozen bit of register q in mapping mp (laundered at the
+    // point of use, so that ballots of it are not hoisted out of the
+    // iteration loop into long-lived scalar registers)
+    __device__ __forceinline__ bool fzbit(int mp, int q) const
+    {
+        uint32_t v = fzb[mp >> 1];
+        asm volatile("" : "+v"(v));
+        return (v >> ((mp & 1) * 16 + q)) & 1;
+    }
+
+    // frozen ballot word [mapping mp][register q] (bit l: lane l's row)
+    __device__ __forceinline__ uint64_t fz(int mp, int q) const
+    {
+        return ballot(fzbit(mp, q));
     }
 
     __device__ __forceinline__ Decoder(const Params &P_, Smem &S_, int lane_)
@@ -155,6 +173,14 @@ struct Decoder {
                 if ((lane >> lb) & 1)
                     r |= 1 << lrow(mp, lb);
             lr[mp] = r;
+        }
+#pragma unroll
+        for (int h = 0; h < 2; h++) {
+            uint32_t b = 0;
+#pragma unroll
+            for (int k = 0; k < 2 * Q; k++)
+                b |= (uint32_t)((fz_word(2 * h + k / Q, k % Q) >> lane) & 1) << k;
+            fzb[h] = b;
         }
     }
 
@@ -176,8 +202,7 @@ struct Decoder {
     // still be read, so only those consult the kept decisions.
     __device__ __forceinline__ float l11(int q, int lo, int hi) const
     {
-        const uint64_t fzq = fz(MA, q);
-        float v = ((fzq >> lane) & 1) ? kInf : 0.0f;
+        float v = fzbit(MA, q) ? kInf : 0.0f;
         if (FRZ) {
             const int rq = rowq(MA, q);
             if (rq + 252 >= lo && rq < hi) {
@@ -588,8 +613,7 @@ struct Decoder {
     // decisions on rows below the frozen prefix fm
     __device__ __forceinline__ uint64_t u_word(int q, int fm)
     {
-        const uint64_t fzq = fz(MA, q);
-        uint64_t u = ballot(R[q] < 0.0f) & ~fzq;
+        uint64_t u = ballot(R[q] < 0.0f && !fzbit(MA, q));
         if (FRZ) {
             const int base = rowq(MA, q);         // lane l holds row base + 4l
             if (fm > base) {
