@@ -35,7 +35,9 @@ OPS_PER_PE = 12
 
 # the kernel one step launches (one launch per step)
 KERNEL = "bp_decode_r10_kernel<true, true>"
-KERNEL_SRC = os.path.join(ROOT, "paper_1505_04979_amd", "csrc", "pbp_r10.hip")
+# sources of that kernel (the traffic record is valid while they are unchanged)
+KERNEL_SRCS = [os.path.join(ROOT, "paper_1505_04979_amd", "csrc", f)
+               for f in ("pbp_r10.hip", "pbp_r10_decoder.h", "pbp_r10.h")]
 TRAFFIC = os.path.join(ROOT, "profiles", "traffic_bp_decode_r10_n1024_3db.txt")
 
 MODES = {
@@ -88,8 +90,11 @@ def time_mode(pbp, torch, code, d_llr, opts, steps, warmup):
 
 def source_digest():
     import hashlib
-    with open(KERNEL_SRC, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+    h = hashlib.sha256()
+    for src in KERNEL_SRCS:
+        with open(src, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
 
 
 def measured_traffic():
