@@ -143,6 +143,22 @@ __device__ __forceinline__ void sync()
         __syncthreads();
 }
 
+// Barrier between stages: only the working R column (and the walk's words
+// and control) must be ordered there.  When R is in LDS, the L messages a
+// stage stores to device memory are next read in the following iteration,
+// after the full barrier that ends each sweep, so they stay in flight.
+template <bool WAVE, int STATE>
+__device__ __forceinline__ void sync_stage()
+{
+    if constexpr (WAVE || STATE == 2) {
+        sync<WAVE>();
+    } else {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+        __builtin_amdgcn_s_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+    }
+}
+
 // LDS bytes of one decoder instance: [u64 xw NW][u64 dw NW][Ctl], then
 // [f32 Rw N] unless STATE == 2, then [f32 ch N] and L (m+1 columns) if
 // STATE == 0
@@ -219,25 +235,51 @@ __device__ __forceinline__ void decode_frame(const DecodeParams &P,
             const int s = M - j;
             const int h = 1 << s;
             const int f = ctl->p[j - 1] << (s + 1);  // frozen rows, column j
-            const float *Rin = (j == 1) ? ch : Rw;
             float *Lj = Lc(j);
             const float *Lj1 = Lc(j + 1);
             // ---- PE updates, eq. (1) ----
-#pragma unroll 8
-            for (int q = (f >> 1) + tid; q < N / 2; q += NT) {
-                const int a = ((q >> s) << (s + 1)) | (q & (h - 1));
-                const int b = a + h;
-                const float La = Lj1[a], Lb = Lj1[b];
-                const float Ra = Rin[a], Rb = Rin[b];
-                const float sm = Lb + Rb;
-                const float g1 = gmin(La, Ra, alpha);
-                Lj[a] = gmin(La, sm, alpha);
-                Lj[b] = Lb + g1;
-                Rw[a] = gmin(Ra, sm, alpha);
-                Rw[b] = Rb + g1;
-            }
+            // kBatch PEs per thread at a time: all their loads are issued
+            // before any of their stores (which may alias as far as the
+            // compiler can tell), so their latencies overlap.  Stage 1 reads
+            // the channel column, the others the working column: two copies
+            // of the loop, so that each pointer keeps its address space.
+            auto sweep = [&](const float *Rin) {
+#pragma unroll 1
+                for (int q0 = (f >> 1) + tid; q0 < N / 2; q0 += kBatch * NT) {
+                    float La[kBatch], Lb[kBatch], Ra[kBatch], Rb[kBatch];
+                    int ia[kBatch];
+#pragma unroll
+                    for (int u = 0; u < kBatch; u++) {
+                        const int q = q0 + u * NT;
+                        const int a = ((q >> s) << (s + 1)) | (q & (h - 1));
+                        ia[u] = a;
+                        if (q < N / 2) {
+                            La[u] = Lj1[a];
+                            Lb[u] = Lj1[a + h];
+                            Ra[u] = Rin[a];
+                            Rb[u] = Rin[a + h];
+                        }
+                    }
+#pragma unroll
+                    for (int u = 0; u < kBatch; u++) {
+                        if (q0 + u * NT < N / 2) {
+                            const int a = ia[u], b = a + h;
+                            const float sm = Lb[u] + Rb[u];
+                            const float g1 = gmin(La[u], Ra[u], alpha);
+                            Lj[a] = gmin(La[u], sm, alpha);
+                            Lj[b] = Lb[u] + g1;
+                            Rw[a] = gmin(Ra[u], sm, alpha);
+                            Rw[b] = Rb[u] + g1;
+                        }
+                    }
+                }
+            };
+            if (j == 1)
+                sweep(ch);
+            else
+                sweep(Rw);
             pe += (N - f) >> 1;
-            sync<WAVE>();
+            sync_stage<WAVE, STATE>();
             if (!P.freezing)
                 continue;
             // ---- CSFG freezing walk (Section III), wavefront 0 ----
@@ -331,8 +373,11 @@ __device__ __forceinline__ void decode_frame(const DecodeParams &P,
                     ctl->walking = walking;
                 }
             }
-            sync<WAVE>();
+            sync_stage<WAVE, STATE>();
         }
+        // the sweep's L stores complete before the stop test reads column 1
+        // and before the next sweep reads them
+        sync<WAVE>();
 
         // ---- decisions, termination ----
         const int fm = P.freezing ? ctl->p[M] : 0;
