@@ -15,7 +15,7 @@ namespace {
 using namespace pbp::generic;
 
 template <int M, bool GSTATE>
-__global__ __launch_bounds__(256) void bp_decode_kernel(DecodeParams P)
+__global__ __launch_bounds__(256, 4) void bp_decode_kernel(DecodeParams P)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     float *gslot = GSTATE ? P.state + (int64_t)blockIdx.x * P.state_stride

@@ -119,8 +119,9 @@ struct DecodeParams {
 // Control words kept in LDS.
 struct Ctl {
     int p[16];        // p[j]: number of frozen CSFGs at stage j (p[0] = 0)
-    int stop;
-    int walking;
+    int walking;      // the walk may still check in this sweep
+    int bad;          // the last check failed
+    int ndiff;        // some word differs in the stop test
 };
 
 template <int M>
@@ -201,6 +202,8 @@ __device__ __forceinline__ void decode_frame(const DecodeParams &P,
     auto Lc = [&](int c) { return Lbase + (size_t)(c - 1) * N; };
     const int lane = tid & 63;
     const bool wave0 = tid < 64;
+    const int wv = tid >> 6;       // wavefront of the group
+    const int nwv = NT >> 6;       // wavefronts in the group
     const float alpha = P.alpha;
     // an opaque thread count keeps the strided loops rolled (a known count
     // of 64 would unroll them N/64 times over and exhaust the registers)
@@ -222,7 +225,6 @@ __device__ __forceinline__ void decode_frame(const DecodeParams &P,
     if (tid == 0) {
         for (int j = 0; j <= M; j++)
             ctl->p[j] = 0;
-        ctl->stop = 0;
     }
     sync<WAVE>();
 
@@ -282,8 +284,10 @@ __device__ __forceinline__ void decode_frame(const DecodeParams &P,
             sync_stage<WAVE, STATE>();
             if (!P.freezing)
                 continue;
-            // ---- CSFG freezing walk (Section III), wavefront 0 ----
-            if (wave0) {
+            // ---- CSFG freezing walk (Section III) ----
+            // The ballots of a check and the freeze writes are shared out
+            // over the group's wavefronts; wavefront 0 transforms and tests.
+            {
                 int pj = max(ctl->p[j], 2 * ctl->p[j - 1]);
                 int walking = ctl->walking;
                 float *L1 = Lc(j + 1);
@@ -293,7 +297,7 @@ __device__ __forceinline__ void decode_frame(const DecodeParams &P,
                     // eq. (2): hard decisions of the CSFG's inputs, the
                     // loads of kBatch words in flight before their ballots
 #pragma unroll 1
-                    for (int w0 = 0; w0 < nw; w0 += kBatch) {
+                    for (int w0 = wv * kBatch; w0 < nw; w0 += nwv * kBatch) {
                         float v[kBatch];
 #pragma unroll
                         for (int u = 0; u < kBatch; u++) {
@@ -310,56 +314,63 @@ __device__ __forceinline__ void decode_frame(const DecodeParams &P,
                                 xw[w0 + u] = bal;
                         }
                     }
-                    sync<true>();
-                    // eq. (3): uhat = xhat F^{(x)s}
-                    uint64_t r[kMaxWordsPerLane];
+                    sync_stage<WAVE, STATE>();
+                    if (wave0) {
+                        // eq. (3): uhat = xhat F^{(x)s}
+                        uint64_t r[kMaxWordsPerLane];
 #pragma unroll
-                    for (int q = 0; q < kMaxWordsPerLane; q++) {
-                        const int w = lane + 64 * q;
-                        r[q] = w < nw ? ffx_word(xw[w]) : 0;
-                    }
-                    ffx_cross(r, nw, lane);
-                    // eq. (4): no frozen position may decode to 1
-                    bool bad = false;
-#pragma unroll
-                    for (int q = 0; q < kMaxWordsPerLane; q++) {
-                        const int w = lane + 64 * q;
-                        if (w < nw) {
-                            uint64_t fz;
-                            if (h >= 64) {
-                                fz = P.frozen_words[(r0 >> 6) + w];
-                            } else {
-                                fz = (P.frozen_words[r0 >> 6] >> (r0 & 63)) &
-                                     ((1ull << h) - 1);
-                            }
-                            bad |= (r[q] & fz) != 0;
+                        for (int q = 0; q < kMaxWordsPerLane; q++) {
+                            const int w = lane + 64 * q;
+                            r[q] = w < nw ? ffx_word(xw[w]) : 0;
                         }
-                    }
-                    if (__any(bad))
-                        break;
-                    // freeze: L at column j+1 := (-1)^xhat inf, keep uhat
+                        ffx_cross(r, nw, lane);
+                        // eq. (4): no frozen position may decode to 1
+                        bool bad = false;
 #pragma unroll
-                    for (int q = 0; q < kMaxWordsPerLane; q++) {
-                        const int w = lane + 64 * q;
-                        if (w < nw) {
-                            // a CSFG may cover sub-CSFGs of later
-                            // stages frozen before it: its decisions
+                        for (int q = 0; q < kMaxWordsPerLane; q++) {
+                            const int w = lane + 64 * q;
+                            if (w < nw) {
+                                uint64_t fz;
+                                if (h >= 64) {
+                                    fz = P.frozen_words[(r0 >> 6) + w];
+                                } else {
+                                    fz = (P.frozen_words[r0 >> 6] >> (r0 & 63)) &
+                                         ((1ull << h) - 1);
+                                }
+                                bad |= (r[q] & fz) != 0;
+                            }
+                        }
+                        bad = __any(bad);
+                        if (!bad) {
+                            // keep uhat; a CSFG may cover sub-CSFGs of
+                            // later stages frozen before it: its decisions
                             // replace theirs
-                            if (h >= 64) {
-                                dw[(r0 >> 6) + w] = r[q];
-                            } else {
-                                const uint64_t msk = ((1ull << h) - 1)
-                                                     << (r0 & 63);
-                                dw[r0 >> 6] = (dw[r0 >> 6] & ~msk) |
-                                              (r[q] << (r0 & 63));
+#pragma unroll
+                            for (int q = 0; q < kMaxWordsPerLane; q++) {
+                                const int w = lane + 64 * q;
+                                if (w < nw) {
+                                    if (h >= 64) {
+                                        dw[(r0 >> 6) + w] = r[q];
+                                    } else {
+                                        const uint64_t msk = ((1ull << h) - 1)
+                                                             << (r0 & 63);
+                                        dw[r0 >> 6] = (dw[r0 >> 6] & ~msk) |
+                                                      (r[q] << (r0 & 63));
+                                    }
+                                }
                             }
                         }
+                        if (lane == 0)
+                            ctl->bad = bad;
                     }
-                    for (int i = lane; i < h; i += 64) {
+                    sync_stage<WAVE, STATE>();
+                    if (ctl->bad)
+                        break;
+                    // freeze: L at column j+1 := (-1)^xhat inf
+                    for (int i = tid; i < h; i += NT) {
                         const bool x = (xw[i >> 6] >> (i & 63)) & 1;
                         L1[r0 + i] = x ? -kInf : kInf;
                     }
-                    sync<true>();
                     pj++;
                     if (P.freeze_walk == 0) {
                         walking = 0;
@@ -367,8 +378,11 @@ __device__ __forceinline__ void decode_frame(const DecodeParams &P,
                     }
                     if (P.freeze_walk == 1)
                         break;
+                    // the next check's ballots reuse the words read above
+                    sync_stage<WAVE, STATE>();
                 }
-                if (lane == 0) {
+                // every thread computed the same pj and walking
+                if (tid == 0) {
                     ctl->p[j] = pj;
                     ctl->walking = walking;
                 }
@@ -381,75 +395,83 @@ __device__ __forceinline__ void decode_frame(const DecodeParams &P,
 
         // ---- decisions, termination ----
         const int fm = P.freezing ? ctl->p[M] : 0;
-        if (wave0) {
-            int stop = P.freezing && fm == N;
-            if (!stop && P.early_stop) {
-                // G-matrix criterion: uhat F^{(x)m} == hard(R + L) at
-                // column 1
-                const float *L1 = Lc(1);
-                uint64_t r[kMaxWordsPerLane];
+        int stop = P.freezing && fm == N;
+        if (!stop && P.early_stop) {
+            // G-matrix criterion: uhat F^{(x)m} == hard(R + L) at column 1;
+            // the ballots are shared out over the wavefronts, wavefront 0
+            // transforms
+            const float *L1 = Lc(1);
 #pragma unroll 1
-                for (int w0 = 0; w0 < NW; w0 += kBatch) {
-                    float rv[kBatch];
+            for (int w0 = wv * kBatch; w0 < NW; w0 += nwv * kBatch) {
+                float rv[kBatch];
 #pragma unroll
-                    for (int u = 0; u < kBatch; u++) {
-                        const int i = 64 * (w0 + u) + lane;
-                        rv[u] = (w0 + u < NW && i < N) ? Rw[i] : 0.0f;
-                    }
-#pragma unroll
-                    for (int u = 0; u < kBatch; u++) {
-                        const int w = w0 + u;
-                        const int i = 64 * w + lane;
-                        bool x = false;
-                        if (w < NW && i < N) {
-                            if (i < fm)
-                                x = (dw[w] >> (i & 63)) & 1;
-                            else
-                                x = !frozen_bit(P.frozen_words, i) && rv[u] < 0.0f;
-                        }
-                        const uint64_t bal = __ballot(x);
-                        if (lane == 0 && w < NW)
-                            xw[w] = bal;
-                    }
+                for (int u = 0; u < kBatch; u++) {
+                    const int i = 64 * (w0 + u) + lane;
+                    rv[u] = (w0 + u < NW && i < N) ? Rw[i] : 0.0f;
                 }
-                sync<true>();
+#pragma unroll
+                for (int u = 0; u < kBatch; u++) {
+                    const int w = w0 + u;
+                    const int i = 64 * w + lane;
+                    bool x = false;
+                    if (w < NW && i < N) {
+                        if (i < fm)
+                            x = (dw[w] >> (i & 63)) & 1;
+                        else
+                            x = !frozen_bit(P.frozen_words, i) && rv[u] < 0.0f;
+                    }
+                    const uint64_t bal = __ballot(x);
+                    if (lane == 0 && w < NW)
+                        xw[w] = bal;
+                }
+            }
+            sync_stage<WAVE, STATE>();
+            if (wave0) {
+                uint64_t r[kMaxWordsPerLane];
 #pragma unroll
                 for (int q = 0; q < kMaxWordsPerLane; q++) {
                     const int w = lane + 64 * q;
                     r[q] = w < NW ? ffx_word(xw[w]) : 0;
                 }
                 ffx_cross(r, NW, lane);
-                bool diff = false;
-#pragma unroll 1
-                for (int w0 = 0; w0 < NW; w0 += kBatch) {
-                    float v[kBatch];
+                // the transformed words replace the source words
+                sync<true>();
 #pragma unroll
-                    for (int u = 0; u < kBatch; u++) {
-                        const int i = 64 * (w0 + u) + lane;
-                        v[u] = (w0 + u < NW && i < N) ? ch[i] + L1[i] : 0.0f;
-                    }
-#pragma unroll
-                    for (int u = 0; u < kBatch; u++) {
-                        const int w = w0 + u;
-                        const uint64_t bal = __ballot(v[u] < 0.0f);
-                        // the lane holding word w compares it
-                        if (w < NW && (w & 63) == lane) {
-                            const int q = w >> 6;
-                            uint64_t mine = r[0];
-                            if (q == 1) mine = r[1];
-                            if (q == 2) mine = r[2];
-                            if (q == 3) mine = r[3];
-                            diff |= mine != bal;
-                        }
-                    }
+                for (int q = 0; q < kMaxWordsPerLane; q++) {
+                    const int w = lane + 64 * q;
+                    if (w < NW)
+                        xw[w] = r[q];
                 }
-                stop = !__any(diff);
+                if (lane == 0)
+                    ctl->ndiff = 0;
             }
-            if (lane == 0)
-                ctl->stop = stop;
+            sync_stage<WAVE, STATE>();
+            bool diff = false;
+#pragma unroll 1
+            for (int w0 = wv * kBatch; w0 < NW; w0 += nwv * kBatch) {
+                float v[kBatch];
+#pragma unroll
+                for (int u = 0; u < kBatch; u++) {
+                    const int i = 64 * (w0 + u) + lane;
+                    v[u] = (w0 + u < NW && i < N) ? ch[i] + L1[i] : 0.0f;
+                }
+#pragma unroll
+                for (int u = 0; u < kBatch; u++) {
+                    const int w = w0 + u;
+                    const uint64_t bal = __ballot(v[u] < 0.0f);
+                    if (w < NW)
+                        diff |= xw[w] != bal;
+                }
+            }
+            if (lane == 0 && diff)
+                ctl->ndiff = 1;
+            sync_stage<WAVE, STATE>();
+            stop = ctl->ndiff == 0;
         }
+        // end of the sweep: every thread has read the control words before
+        // the next sweep changes them
         sync<WAVE>();
-        if (ctl->stop)
+        if (stop)
             break;
     }
     if (t > P.max_iter)

@@ -149,7 +149,7 @@ __global__ __launch_bounds__(64, 2) void class_kernel(ClassParams P)
 constexpr int kWgThreads = 256;
 
 template <int M>
-__global__ __launch_bounds__(kWgThreads) void class_wg_kernel(ClassParams P)
+__global__ __launch_bounds__(kWgThreads, 4) void class_wg_kernel(ClassParams P)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ int s_q;
