@@ -143,10 +143,11 @@ typedef struct pbp_mixed_plan pbp_mixed_plan;
 /* Launch configuration.
  *  order         0: the queue takes frames in the caller's order;
  *                1: longest code first (a counting sort on the device)
- *  waves_per_cu  resident one-wavefront groups per compute unit, 1..8
+ *  waves_per_cu  resident one-wavefront groups per compute unit, 1..16
  *                (each decodes one frame at a time); codes with N >= 2048
  *                are decoded by 256-thread groups, waves_per_cu / 2 of them
- *                (at least 1) per compute unit */
+ *                (at least 1, at most 4) per compute unit.  No kernel is
+ *                given more groups than its occupancy allows. */
 typedef struct {
     int32_t order;
     int32_t waves_per_cu;
@@ -157,7 +158,7 @@ typedef struct {
  * memory: the queue (4 B per frame) and, when a code has N >= 2048, one
  * message slot per resident workgroup ((m+1) 2^m floats for the longest
  * such code, 4 workgroups per compute unit).
- * Default configuration: {1, 8}.  Errors: PBP_EINVAL, PBP_ENOMEM,
+ * Default configuration: {0, 16}.  Errors: PBP_EINVAL, PBP_ENOMEM,
  * PBP_EDEVICE. */
 int32_t pbp_mixed_plan_create(const pbp_code *const *codes, int32_t ncodes,
                               int64_t max_frames, pbp_mixed_plan **out);
@@ -195,8 +196,8 @@ int32_t pbp_decode_mixed(pbp_mixed_plan *plan, const int32_t *code_of_frame,
                          const pbp_decode_opts *opts, uint8_t *info_out,
                          int32_t *iters_out, int64_t *pe_out, void *stream);
 
-/* Autotuner: time every candidate configuration (order 0/1 x 2, 4, 6 or 8
- * wavefronts per compute unit) on the given batch, one untimed and `reps`
+/* Autotuner: time every candidate configuration (order 0/1 x 4, 8, 12 or
+ * 16 wavefronts per compute unit) on the given batch, one untimed and `reps`
  * timed launches each, and keep the fastest in the plan (also written to
  * *best if not NULL).  Results are cached for the life of the process per
  * (device, the plan's (N, K) list, early_stop, freezing): a later call with

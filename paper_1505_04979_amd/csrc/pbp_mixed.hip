@@ -35,7 +35,8 @@
 namespace {
 
 constexpr int kMaxCodes = 16;
-constexpr int kMaxWavesPerCu = 8;
+constexpr int kMaxWavesPerCu = 16;
+constexpr int kMaxLongGroupsPerCu = 4;   // 256-thread groups of long codes
 constexpr int64_t kMaxFrames = 1ll << 30;
 
 struct CodeDesc {
@@ -298,7 +299,7 @@ struct pbp_mixed_plan {
     int64_t slot_floats = 0;
     int64_t *d_stats = nullptr;     // 3 per wavefront per code
     int last_waves[kMaxCodes] = {};
-    pbp_mixed_config cfg{1, 8};
+    pbp_mixed_config cfg{0, 16};
 };
 
 namespace {
@@ -411,10 +412,18 @@ hipError_t enqueue(pbp_mixed_plan *p, const pbp_mixed_config &cfg,
             return hipErrorInvalidValue;
         // resident groups per compute unit: waves_per_cu one-wavefront
         // groups, or half as many 256-thread groups (their wavefronts wait
-        // on memory, so twice the wavefronts are resident)
-        int64_t grid = (int64_t)p->cus *
-                       (L.threads == 64 ? cfg.waves_per_cu
-                                        : std::max(1, cfg.waves_per_cu / 2));
+        // on memory, so twice the wavefronts are resident, and at most one
+        // per device slot), never more than the kernel's occupancy allows
+        int per_cu = L.threads == 64
+                         ? cfg.waves_per_cu
+                         : std::min(kMaxLongGroupsPerCu,
+                                    std::max(1, cfg.waves_per_cu / 2));
+        int occ = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, L.kern, L.threads,
+                                                         L.lds) == hipSuccess &&
+            occ >= 1 && occ < per_cu)
+            per_cu = occ;
+        int64_t grid = (int64_t)p->cus * per_cu;
         if (grid > B)
             grid = B;
         ClassParams P{};
@@ -493,7 +502,7 @@ extern "C" int32_t pbp_mixed_plan_create(const pbp_code *const *codes,
         return PBP_EDEVICE;
     }
     const int64_t waves = (int64_t)p->cus * kMaxWavesPerCu;
-    const int64_t groups = waves / 2;                 // long-code workgroups
+    const int64_t groups = (int64_t)p->cus * kMaxLongGroupsPerCu;
     int32_t st = PBP_OK;
     // codes longer than 1024 keep L in a slot per resident workgroup
     if (max_long)
@@ -628,8 +637,8 @@ extern "C" int32_t pbp_mixed_plan_tune(pbp_mixed_plan *plan,
         (void)hipEventDestroy(e0);
         return PBP_EDEVICE;
     }
-    pbp_mixed_config cand[] = {{0, 2}, {0, 4}, {0, 6}, {0, 8},
-                               {1, 2}, {1, 4}, {1, 6}, {1, 8}};
+    pbp_mixed_config cand[] = {{0, 4}, {0, 8}, {0, 12}, {0, 16},
+                               {1, 4}, {1, 8}, {1, 12}, {1, 16}};
     float best_ms = 0.0f;
     pbp_mixed_config best_cfg = plan->cfg;
     int32_t status = PBP_OK;

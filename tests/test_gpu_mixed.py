@@ -82,7 +82,7 @@ def test_mixed_parity(env, mode):
     oracle_check(dims, batch, out, mode, 60)
 
 
-@pytest.mark.parametrize("cfg", [(0, 1), (0, 3), (1, 2), (1, 8)])
+@pytest.mark.parametrize("cfg", [(0, 1), (0, 3), (1, 2), (1, 8), (1, 16)])
 def test_configs_give_identical_results(env, cfg):
     pbp, torch = env
     dims = [(64, 32), (1024, 512), (2048, 1024), (128, 100), (1024, 300)]
@@ -183,7 +183,7 @@ def test_tune_picks_and_caches(env):
     plan = pbp.MixedPlan(codes_of(pbp, dims), 600)
     best = pbp.pbp_mixed_plan_tune(plan, cof, lo, io, llr, info_bytes=nbits,
                                    max_iter=60, reps=1, **MODES["es_frz"])
-    assert best[0] in (0, 1) and best[1] in (2, 4, 6, 8)
+    assert best[0] in (0, 1) and best[1] in (4, 8, 12, 16)
     assert plan.config == best
     # a second plan with the same codes and mode takes the cached result
     plan2 = pbp.MixedPlan(codes_of(pbp, dims), 600)
@@ -210,7 +210,7 @@ def test_rejects_bad_arguments(env):
     with pytest.raises(pbp.PbpError):
         plan.config = (2, 4)
     with pytest.raises(pbp.PbpError):
-        plan.config = (1, 9)
+        plan.config = (1, 17)
     z = torch.zeros(11, dtype=torch.int32, device="cuda")
     zl = torch.zeros(11, dtype=torch.int64, device="cuda")
     buf = torch.zeros(64 * 11, dtype=torch.float32, device="cuda")
