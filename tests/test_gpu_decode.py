@@ -211,3 +211,19 @@ def test_unaligned_buffers_take_the_generic_kernel(env):
     g = {k: v.cpu().numpy() for k, v in o.items()}
     r = oracle.decode(llr, fz, soft=True, **kw)
     assert_parity(g, r, K, fz)
+
+
+def test_long_code_batch_sampled_parity(env):
+    """The long-code benchmark's launch shape ((16384, 8192) code, 2.0 dB,
+    4096 frames, 60 iterations, early stop + freezing), checked on sampled
+    frames."""
+    N, K, B = 16384, 8192, 4096
+    print(f"[parity] long batch N={N} B={B}", flush=True)
+    fz = frozen_mask(N, K)
+    u, x, llr = make_frames(N, K, B, 2.0, stream=2025)
+    kw = MODES["es_frz_total"]
+    g = gpu_decode(env, N, K, llr, max_iter=60, **kw)
+    idx = np.random.default_rng(1).choice(B, 3, replace=False)
+    r = oracle.decode(llr[idx], fz, max_iter=60, soft=True, **kw)
+    sub = {k: v[idx] for k, v in g.items()}
+    assert_parity(sub, r, K, fz)

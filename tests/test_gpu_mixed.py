@@ -216,3 +216,41 @@ def test_rejects_bad_arguments(env):
     buf = torch.zeros(64 * 11, dtype=torch.float32, device="cuda")
     with pytest.raises(pbp.PbpError):   # more frames than the plan holds
         pbp.pbp_decode_mixed(plan, z, zl, zl, buf, info_bytes=64)
+
+
+def test_full_size_mixed_batch_sampled(env):
+    """The mixed workload at full size (2^20 frames over the nine codes,
+    Eb/N0 uniform in [1, 4] dB, 60 iterations) in the tuned launch
+    configuration.  To keep input generation short, 2^16 distinct frames are
+    repeated 16 times (each copy with its own offsets): every copy must
+    decode identically, and sampled frames of every code match the oracle."""
+    pbp, torch = env
+    U, REP = 1 << 16, 16
+    B = U * REP
+    print(f"[mixed] full size B={B}", flush=True)
+    batch = make_mixed(MIX, U, stream=48)
+    cof, ebn0, lo, io, llr, info = batch
+    nllr, nbits = len(llr), int(sum(len(i) for i in info))
+    k = np.repeat(np.arange(REP, dtype=np.int64), U)
+    d = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    d_cof = d(np.tile(cof, REP))
+    d_lo = d(np.tile(lo, REP) + k * nllr)
+    d_io = d(np.tile(io, REP) + k * nbits)
+    d_llr = d(llr).repeat(REP)
+    plan = pbp.MixedPlan(codes_of(pbp, MIX), B)
+    plan.config = (0, 16)
+    out = pbp.pbp_decode_mixed(plan, d_cof, d_lo, d_io, d_llr,
+                               info_bytes=nbits * REP, max_iter=60,
+                               **MODES["es_frz"])
+    torch.cuda.synchronize()
+    for key in ("iters", "pe", "info"):
+        v = out[key].view(REP, -1)
+        assert torch.equal(v, v[:1].expand_as(v)), key
+    first = {key: v[:U] if key != "info" else v[:nbits]
+             for key, v in out.items()}
+    rng = np.random.default_rng(2)
+    frames = np.concatenate([rng.choice(np.flatnonzero(cof == c), 3,
+                                        replace=False)
+                             for c in range(len(MIX))])
+    oracle_check(MIX, batch, first, "es_frz", 60, frames=frames)
+    assert 0.9 < pbp.pbp_mixed_plan_fill(plan) <= 1.0
