@@ -365,7 +365,8 @@ struct Decoder {
     template <int J, int SLOT>
     __device__ __forceinline__ void slot_step(int f)
     {
-        if (f <= SLOT * 256)
+        // the common case (nothing of the slot frozen) falls through
+        if (__builtin_expect(f <= SLOT * 256, 1))
             run_slot<J, SLOT>();
         else if (f < SLOT * 256 + 256)
             pe_slot_masked<J, 0, SLOT>(f);
@@ -453,7 +454,8 @@ struct Decoder {
             for (int lb = 0; lb < 6; lb++)
                 if (lrow(MP, lb) < SH)
                     w = ffx_lane(w, lb);
-            if ((w & fzl) != 0)
+            // most checks fail here
+            if (__builtin_expect((w & fzl) != 0, 1))
                 return false;
         }
 #pragma unroll
@@ -567,7 +569,7 @@ struct Decoder {
     __device__ __forceinline__ void freeze_walk()
     {
         constexpr int SH = M - J;
-        if (!P.freezing)
+        if (__builtin_expect(!P.freezing, 0))
             return;
         int pj = max(p[J], 2 * p[J - 1]);
         const int k0 = pj;
@@ -645,7 +647,7 @@ struct Decoder {
 #pragma unroll
             for (int lb = 0; lb < 6; lb++)
                 w = ffx_lane(w, lb);
-            if (w != X[Q - 1])
+            if (__builtin_expect(w != X[Q - 1], 1))
                 return false;
         }
         uint64_t U[Q];

@@ -280,6 +280,10 @@ __global__ __launch_bounds__(Shape<M>::NT) void unrolled_backward_kernel(BwdPara
                 }
             }
             __syncthreads();
+            // this thread's share of the scale gradients, per stage; reduced
+            // over the group once per iteration, off the stages' critical path
+            float accL[M], accR[M];
+#pragma unroll
             for (int j = M; j >= 1; j--) {
                 const float aL = scale_at(P.alpha, ((int64_t)t * M + (j - 1)) * 2);
                 const float aR = scale_at(P.alpha, ((int64_t)t * M + (j - 1)) * 2 + 1);
@@ -334,18 +338,25 @@ __global__ __launch_bounds__(Shape<M>::NT) void unrolled_backward_kernel(BwdPara
                     dRo[a] = dRa;
                     dRo[b] = dRb;
                 }
+                accL[j - 1] = daL;
+                accR[j - 1] = daR;
+                __syncthreads();
+            }
+#pragma unroll
+            for (int k = 0; k < M; k++) {
+                float vL = accL[k], vR = accR[k];
                 for (int o = 32; o >= 1; o >>= 1) {
-                    daL += __shfl_xor(daL, o, 64);
-                    daR += __shfl_xor(daR, o, 64);
+                    vL += __shfl_xor(vL, o, 64);
+                    vR += __shfl_xor(vR, o, 64);
                 }
                 if (lane == 0) {
-                    red[((j - 1) * NW + wv) * 2] = daL;
-                    red[((j - 1) * NW + wv) * 2 + 1] = daR;
+                    red[(k * NW + wv) * 2] = vL;
+                    red[(k * NW + wv) * 2 + 1] = vR;
                 }
-                __syncthreads();
             }
             for (int i = tid; i < N; i += NT)
                 dC[i] += dR[(1 & 1) * N + i];
+            __syncthreads();
             if (tid < 2 * M) {
                 float acc = 0.0f;
                 for (int w = 0; w < NW; w++)
