@@ -244,7 +244,9 @@ int32_t pbp_unrolled_forward(const pbp_code *code, const float *llr, int64_t B,
  * (the frozen prior and what it produces) are constants and take no
  * gradient.
  *   llr, alpha, T  as given to the forward call
- *   ckpt           device, the forward call's checkpoints (NULL if N = 2)
+ *   ckpt           device, the forward call's checkpoints (NULL if N = 2);
+ *                  consumed: the call overwrites them with adjoints, so a
+ *                  second backward call needs a new forward call
  *   dout           device, B x N FP32, the gradient at the output
  *   dalpha_frame   device, B x T x m x 2 FP32, written: each frame's
  *                  contribution to the scale gradient (workspace owned by
@@ -255,7 +257,7 @@ int32_t pbp_unrolled_forward(const pbp_code *code, const float *llr, int64_t B,
  * Errors: as pbp_unrolled_forward. */
 int32_t pbp_unrolled_backward(const pbp_code *code, const float *llr,
                               int64_t B, int32_t T, const float *alpha,
-                              const float *ckpt, const float *dout,
+                              float *ckpt, const float *dout,
                               float *dalpha_frame, float *dalpha, float *dllr,
                               void *stream);
 

@@ -9,10 +9,11 @@
 // T-iteration BP).  The output is R^T at column m+1.
 //
 // One workgroup owns one frame at a time (grid-stride over frames), one
-// thread per PE of a stage, the message columns in LDS.  The forward writes
-// the L state at the start of every iteration (columns 2..m) to a caller
-// buffer; the backward reloads it, recomputes that iteration's R sweep, and
-// runs the stages in reverse with the adjoints in LDS.  Scale gradients are
+// thread per PE of a stage.  The forward keeps the message columns in LDS
+// and writes the L state at the start of every iteration (columns 2..m) to a
+// caller buffer.  The backward recomputes each iteration's R sweep from
+// that checkpoint, then runs the stages in reverse; the adjoint of L takes
+// the place of the checkpoint it was computed from.  Scale gradients are
 // reduced per frame in a fixed order, then over frames in FP64, so results
 // do not depend on scheduling.
 //
@@ -81,8 +82,6 @@ struct Shape {
     static constexpr int NT = H < 64 ? 64 : H;      // threads per workgroup
     static constexpr int NW = NT / 64;              // wavefronts
     static constexpr int YR = (N + NT - 1) / NT;    // LLRs per thread
-    // checkpoint floats per thread (L at columns 2..m)
-    static constexpr int CR = M > 1 ? ((M - 1) * N + NT - 1) / NT : 1;
 };
 
 struct FwdParams {
@@ -101,7 +100,7 @@ struct BwdParams {
     int T;
     const float *alpha;
     const uint64_t *frozen;
-    const float *ckpt;
+    float *ckpt;              // read, then overwritten with L adjoints
     const float *dout;        // B x N
     float *dalpha_frame;      // B x T x m x 2
     float *dllr;              // B x N, or null
@@ -117,8 +116,7 @@ template <int M>
 size_t bwd_lds_bytes()
 {
     using S = Shape<M>;
-    return sizeof(float) * ((size_t)(M + M + 1 + (M - 1) + 2 + 1) * S::N +
-                            (size_t)M * S::NW * 2);
+    return sizeof(float) * ((size_t)(M + 2) * S::N + (size_t)M * S::NW * 2);
 }
 
 template <int M>
@@ -189,86 +187,96 @@ __global__ __launch_bounds__(Shape<M>::NT) void unrolled_forward_kernel(FwdParam
     }
 }
 
-// this thread's share of the checkpoint of iteration t of frame f
-template <int M>
-__device__ __forceinline__ void load_ckpt(const BwdParams &P, int t, int64_t f,
-                                          int tid, float (&cv)[Shape<M>::CR])
+// Barrier that orders LDS only (device-memory accesses of a stage are
+// ordered by the full barrier that ends each iteration).
+__device__ __forceinline__ void sync_lds()
 {
-    using S = Shape<M>;
-    const float *ck = P.ckpt + ((int64_t)t * P.B + f) * (M - 1) * S::N;
-#pragma unroll
-    for (int k = 0; k < S::CR; k++) {
-        const int i = tid + k * S::NT;
-        cv[k] = i < (M - 1) * S::N ? ck[i] : 0.0f;
-    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
 
+// Backward pass.  L^{t-1} is read straight from the checkpoint of
+// iteration t (device memory, mostly in L2), and the adjoint of L^{t-1} is
+// written over it: stage j reads rows a, b of column j+1 and then, in the
+// same thread, replaces them with their adjoints, which iteration t-1 reads.
+// LDS holds only R^t (columns 1..m) and two columns of its adjoint, so two
+// workgroups fit on a compute unit.
 template <int M>
-__global__ __launch_bounds__(Shape<M>::NT) void unrolled_backward_kernel(BwdParams P)
+__global__ __launch_bounds__(Shape<M>::NT, 4) void unrolled_backward_kernel(BwdParams P)
 {
     using S = Shape<M>;
     constexpr int N = S::N, H = S::H, NT = S::NT, NW = S::NW;
     extern __shared__ __align__(16) float sm[];
-    float *Lp = sm;                     // L^{t-1}, column c (2..m+1) at (c-2)*N
-    float *Rc = Lp + M * N;             // R^t, column c (1..m+1) at (c-1)*N
-    float *dL = Rc + (M + 1) * N;       // adjoint of L, column c (2..m) at (c-2)*N
-    float *dR = dL + (M - 1) * N;       // adjoint of R, two columns by parity
-    float *dC = dR + 2 * N;             // adjoint of the channel LLRs
-    float *red = dC + N;                // [m][NW][2] wavefront partial sums
+    float *Rc = sm;                     // R^t, column c (1..m) at (c-1)*N
+    float *dR = Rc + M * N;             // adjoint of R, two columns by parity
+    float *red = dR + 2 * N;            // [m][NW][2] wavefront partial sums
     const int tid = (int)threadIdx.x;
     const int lane = tid & 63, wv = tid >> 6;
 
     for (int64_t f = blockIdx.x; f < P.B; f += gridDim.x) {
-        // the frame's LLRs stay in registers; the checkpoint of the next
-        // iteration (in reverse order) is loaded into registers while the
-        // current one is processed
-        float yv[S::YR], dv[S::YR], cv[S::CR];
+        // the frame's LLRs, output gradient and channel gradient stay in
+        // registers
+        float yv[S::YR], dv[S::YR], dc[S::YR];
 #pragma unroll
         for (int k = 0; k < S::YR; k++) {
             const int i = tid + k * NT;
             yv[k] = i < N ? P.llr[f * N + i] : 0.0f;
             dv[k] = i < N ? P.dout[f * N + i] : 0.0f;
-        }
-        load_ckpt<M>(P, P.T - 1, f, tid, cv);
-        for (int i = tid; i < N; i += NT) {
-            Lp[(M - 1) * N + i] = frozen_at(P.frozen, i) ? kInf : 0.0f;
-            for (int c = 0; c < M - 1; c++)
-                dL[c * N + i] = 0.0f;
-            dC[i] = 0.0f;
+            dc[k] = 0.0f;
         }
         for (int t = P.T - 1; t >= 0; t--) {
-#pragma unroll
-            for (int k = 0; k < S::CR; k++) {
-                const int i = tid + k * NT;
-                if (i < (M - 1) * N)
-                    Lp[i] = cv[k];
-            }
+            // L^{t-1} at columns 2..m, replaced by its adjoint below
+            float *ck = P.ckpt + ((int64_t)t * P.B + f) * (M - 1) * N;
+            // adjoint of L^t at columns 2..m (zero after the last iteration)
+            const float *dk = t + 1 < P.T
+                                  ? P.ckpt + ((int64_t)(t + 1) * P.B + f) * (M - 1) * N
+                                  : nullptr;
+            auto lprev = [&](int c, int r) -> float {
+                return c == M + 1 ? (frozen_at(P.frozen, r) ? kInf : 0.0f)
+                                  : ck[(c - 2) * N + r];
+            };
 #pragma unroll
             for (int k = 0; k < S::YR; k++) {
                 const int i = tid + k * NT;
                 if (i < N)
                     Rc[i] = yv[k];
             }
-            if (t > 0)
-                load_ckpt<M>(P, t - 1, f, tid, cv);
-            __syncthreads();
-            // the R sweep of iteration t+1
-            for (int j = 1; j <= M; j++) {
+            sync_lds();
+            // rows of this thread's PE at stage j
+            auto row_a = [&](int j) {
+                const int sh = M - j;
+                return ((tid >> sh) << (sh + 1)) | (tid & ((1 << sh) - 1));
+            };
+            // the R sweep of iteration t+1; each stage's L^{t-1} inputs are
+            // requested one stage ahead, so their latency overlaps a stage
+            float pLa = 0.0f, pLb = 0.0f;
+            if (tid < H && M > 1) {
+                const int a = row_a(1);
+                pLa = lprev(2, a);
+                pLb = lprev(2, a + (1 << (M - 1)));
+            }
+#pragma unroll
+            for (int j = 1; j < M; j++) {
                 const float aR = scale_at(P.alpha, ((int64_t)t * M + (j - 1)) * 2 + 1);
                 const int sh = M - j, h = 1 << sh;
                 if (tid < H) {
-                    const int a = ((tid >> sh) << (sh + 1)) | (tid & (h - 1));
+                    const int a = row_a(j);
                     const int b = a + h;
-                    const float *Lc = Lp + (j - 1) * N;
                     const float *Ri = Rc + (j - 1) * N;
                     float *Ro = Rc + j * N;
-                    const float La = Lc[a], Lb = Lc[b];
+                    const float La = pLa, Lb = pLb;
+                    if (j + 1 < M) {
+                        const int an = row_a(j + 1);
+                        pLa = lprev(j + 2, an);
+                        pLb = lprev(j + 2, an + (h >> 1));
+                    }
                     const float Ra = Ri[a], Rb = Ri[b];
                     const float s = Lb + Rb;
                     Ro[a] = aR * g0(Ra, s);
                     Ro[b] = Rb + aR * g0(La, Ra);
                 }
-                __syncthreads();
+                sync_lds();
             }
             {
                 float *d = dR + ((M + 1) & 1) * N;
@@ -279,10 +287,26 @@ __global__ __launch_bounds__(Shape<M>::NT) void unrolled_backward_kernel(BwdPara
                         d[i] = t == P.T - 1 ? dv[k] : 0.0f;
                 }
             }
-            __syncthreads();
+            sync_lds();
             // this thread's share of the scale gradients, per stage; reduced
             // over the group once per iteration, off the stages' critical path
             float accL[M], accR[M];
+            // the inputs from device memory of stage j (L^{t-1} at column
+            // j+1 and the adjoint of L^t at column j), one stage ahead
+            float qLa = 0.0f, qLb = 0.0f, qiLa = 0.0f, qiLb = 0.0f;
+            auto fetch = [&](int j) {
+                const int a = row_a(j), b = a + (1 << (M - j));
+                qLa = lprev(j + 1, a);
+                qLb = lprev(j + 1, b);
+                qiLa = 0.0f;
+                qiLb = 0.0f;
+                if (j >= 2 && dk) {
+                    qiLa = dk[(j - 2) * N + a];                   // column j
+                    qiLb = dk[(j - 2) * N + b];
+                }
+            };
+            if (tid < H)
+                fetch(M);
 #pragma unroll
             for (int j = M; j >= 1; j--) {
                 const float aL = scale_at(P.alpha, ((int64_t)t * M + (j - 1)) * 2);
@@ -290,25 +314,25 @@ __global__ __launch_bounds__(Shape<M>::NT) void unrolled_backward_kernel(BwdPara
                 const int sh = M - j, h = 1 << sh;
                 float daL = 0.0f, daR = 0.0f;
                 if (tid < H) {
-                    const int a = ((tid >> sh) << (sh + 1)) | (tid & (h - 1));
+                    const int a = row_a(j);
                     const int b = a + h;
-                    const float *Lc = Lp + (j - 1) * N;
                     const float *Ri = Rc + (j - 1) * N;
                     const float *dRi = dR + ((j + 1) & 1) * N;   // column j+1
                     float *dRo = dR + (j & 1) * N;               // column j
-                    const float La = Lc[a], Lb = Lc[b];
+                    const float La = qLa, Lb = qLb;
+                    const float iLa = qiLa, iLb = qiLb;
+                    float oLa = 0.0f, oLb = 0.0f;
+                    // stage j-1 reads column j, which this stage leaves as is
+                    if (j > 1)
+                        fetch(j - 1);
                     const float Ra = Ri[a], Rb = Ri[b];
                     const float s = Lb + Rb;
                     const float gA = g0(La, s), g1 = g0(La, Ra), gB = g0(Ra, s);
                     // adjoints of the four outputs; infinite outputs are constants
                     const bool fLa = finite(aL * gA), fLb = finite(Lb + aL * g1);
                     const bool fRa = finite(aR * gB), fRb = finite(Rb + aR * g1);
-                    float oLa = 0.0f, oLb = 0.0f;
-                    if (j >= 2) {
-                        const float *dLc = dL + (j - 2) * N;     // column j
-                        oLa = fLa ? dLc[a] : 0.0f;
-                        oLb = fLb ? dLc[b] : 0.0f;
-                    }
+                    oLa = fLa ? iLa : 0.0f;
+                    oLb = fLb ? iLb : 0.0f;
                     const float oRa = fRa ? dRi[a] : 0.0f;
                     const float oRb = fRb ? dRi[b] : 0.0f;
                     if (fLa)
@@ -331,16 +355,17 @@ __global__ __launch_bounds__(Shape<M>::NT) void unrolled_backward_kernel(BwdPara
                         dRb += ds;
                     }
                     if (j + 1 <= M) {
-                        float *dLw = dL + (j - 1) * N;           // column j+1
-                        dLw[a] = finite(La) ? dLa : 0.0f;
-                        dLw[b] = finite(Lb) ? dLb : 0.0f;
+                        // column j+1 of L^{t-1} is read by this stage only,
+                        // and only by this thread: its adjoint takes its place
+                        ck[(j - 1) * N + a] = finite(La) ? dLa : 0.0f;
+                        ck[(j - 1) * N + b] = finite(Lb) ? dLb : 0.0f;
                     }
                     dRo[a] = dRa;
                     dRo[b] = dRb;
                 }
                 accL[j - 1] = daL;
                 accR[j - 1] = daR;
-                __syncthreads();
+                sync_lds();
             }
 #pragma unroll
             for (int k = 0; k < M; k++) {
@@ -354,20 +379,31 @@ __global__ __launch_bounds__(Shape<M>::NT) void unrolled_backward_kernel(BwdPara
                     red[(k * NW + wv) * 2 + 1] = vR;
                 }
             }
-            for (int i = tid; i < N; i += NT)
-                dC[i] += dR[(1 & 1) * N + i];
-            __syncthreads();
+#pragma unroll
+            for (int k = 0; k < S::YR; k++) {
+                const int i = tid + k * NT;
+                if (i < N)
+                    dc[k] += dR[(1 & 1) * N + i];
+            }
+            sync_lds();
             if (tid < 2 * M) {
                 float acc = 0.0f;
                 for (int w = 0; w < NW; w++)
                     acc += red[((tid >> 1) * NW + w) * 2 + (tid & 1)];
                 P.dalpha_frame[((f * P.T + t) * M) * 2 + tid] = acc;
             }
+            // the adjoints written over this iteration's checkpoint are read
+            // by other threads in the next one
             __syncthreads();
         }
-        if (P.dllr)
-            for (int i = tid; i < N; i += NT)
-                P.dllr[f * N + i] = dC[i];
+        if (P.dllr) {
+#pragma unroll
+            for (int k = 0; k < S::YR; k++) {
+                const int i = tid + k * NT;
+                if (i < N)
+                    P.dllr[f * N + i] = dc[k];
+            }
+        }
         __syncthreads();
     }
 }
@@ -424,7 +460,7 @@ hipError_t launch_backward(const pbp_code *c, BwdParams &P, hipStream_t st)
                                        (int)lds);
     if (e != hipSuccess)
         return e;
-    hipLaunchKernelGGL(kern, dim3((unsigned)frames_grid(c, P.B, 4)),
+    hipLaunchKernelGGL(kern, dim3((unsigned)frames_grid(c, P.B, 2)),
                        dim3(Shape<M>::NT), lds, st, P);
     return hipGetLastError();
 }
@@ -496,7 +532,7 @@ extern "C" int32_t pbp_unrolled_forward(const pbp_code *code, const float *llr,
 
 extern "C" int32_t pbp_unrolled_backward(const pbp_code *code, const float *llr,
                                          int64_t B, int32_t T,
-                                         const float *alpha, const float *ckpt,
+                                         const float *alpha, float *ckpt,
                                          const float *dout, float *dalpha_frame,
                                          float *dalpha, float *dllr,
                                          void *stream)
