@@ -184,7 +184,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-reference-modes", action="store_true")
     ap.add_argument("--workload", default="n1024",
-                    choices=["n1024", "n16384", "mixed", "unrolled"],
+                    choices=["n1024", "n16384", "mixed", "unrolled", "sweep"],
                     help="n1024: the headline line (default); n16384: the "
                          "long-code decoder; mixed: the mixed-code persistent "
                          "decoder; unrolled: one training step of the "
@@ -207,7 +207,7 @@ def main():
         return
     if args.workload != "n1024":
         fn = {"n16384": bench_long_code, "mixed": bench_mixed,
-              "unrolled": bench_unrolled}[args.workload]
+              "unrolled": bench_unrolled, "sweep": bench_sweep}[args.workload]
         print(json.dumps(fn(args, pbp, torch)), flush=True)
         return
 
@@ -529,6 +529,74 @@ def bench_unrolled(args, pbp, torch):
                           "kernel": "unrolled_forward_kernel<10>"},
         valu_forward={"achieved": round(OPS_PER_PE * pe / (fwd_ms / 1e3) / 1e12, 3),
                       "peak": round(VALU_PEAK_TOPS, 3), "unit": "TOP/s"})
+
+
+SWEEP_MODES = {
+    "plain40": dict(early_stop=False, freezing=False),
+    "early_stop": dict(early_stop=True, freezing=False),
+    "es_freeze_total": dict(early_stop=True, freezing=True, freeze_input=1,
+                            freeze_walk=0),
+    "es_freeze_r": dict(early_stop=True, freezing=True, freeze_input=0,
+                        freeze_walk=0),
+    "freeze_only": dict(early_stop=False, freezing=True, freeze_input=1,
+                        freeze_walk=0),
+    "es_freeze_stage": dict(early_stop=True, freezing=True, freeze_input=1,
+                            freeze_walk=1),
+    "es_freeze_greedy": dict(early_stop=True, freezing=True, freeze_input=1,
+                             freeze_walk=2),
+}
+
+
+def bench_sweep(args, pbp, torch):
+    """The (1024, 512) code over Eb/N0 1.0 .. 3.5 dB: every decoding mode
+    (plain, early stop, early stop with each freezing reading, freezing
+    alone) on the same LLRs per point; error rate, iterations, PE updates
+    per frame and decode rate."""
+    N, K, max_iter, alpha = 1024, 512, 40, 0.9375
+    B = args.batch or (1 << 18)
+    frozen = pbp.pbp_construct(N, K, 0.0)
+    code = pbp.Code(N, K, frozen)
+    points = [1.0, 1.5, 2.0, 2.5, 3.0, 3.5]
+    table = []
+    total_ms = 0.0
+    for k, eb in enumerate(points):
+        info, d_llr = make_inputs(pbp, torch, code, frozen, N, K, B, eb,
+                                  stream=(2 << 16) + k)
+        row = {"ebn0_db": eb}
+        for name, mode in SWEEP_MODES.items():
+            opts = dict(mode, max_iter=max_iter, alpha=alpha)
+            out = pbp.pbp_decode(code, d_llr, **opts)
+            ms = _timed(torch, lambda: pbp.pbp_decode(code, d_llr, out=out,
+                                                      **opts), 1, 0)
+            total_ms += ms
+            errs = int(np.sum(np.any(out["info"].cpu().numpy() != info,
+                                     axis=1)))
+            lo, hi = wilson(errs, B, 1.959963984540054)
+            row[name] = {"fer": errs / B, "fer_ci95": [lo, hi],
+                         "avg_iters": round(float(out["iters"].float().mean()), 3),
+                         "pe_per_frame": round(float(out["pe"].double().mean()), 1),
+                         "mbps": round(B * K / ms / 1e3, 1)}
+        table.append(row)
+        del d_llr
+    at3 = next(r for r in table if r["ebn0_db"] == 3.0)
+    base, es, fz = at3["plain40"], at3["early_stop"], at3["es_freeze_total"]
+    ctx = {"iterations_vs_plain40": round(1 - fz["avg_iters"] / base["avg_iters"], 4),
+           "iterations_vs_early_stop": round(1 - fz["avg_iters"] / es["avg_iters"], 4),
+           "pe_vs_plain40": round(1 - fz["pe_per_frame"] / base["pe_per_frame"], 4),
+           "pe_vs_early_stop": round(1 - fz["pe_per_frame"] / es["pe_per_frame"], 4)}
+    return _line(
+        "FER / iterations / PE updates per frame over Eb/N0, N=1024 R=1/2, "
+        "all decoding modes", round(fz["mbps"], 2), "Mbit/s (3.0 dB, early "
+        "stop + freezing)", 1, 0, total_ms,
+        {"workload": "(1024,512) code, Eb/N0 1.0-3.5 dB, "
+                     f"{B} frames per point, 7 modes on the same LLRs",
+         "frames_per_point": B, "max_iter": max_iter, "alpha": alpha},
+        reductions_at_3db=ctx,
+        paper_reductions_at_3db={"iterations_vs_plain40": 0.46,
+                                 "iterations_vs_early_stop": 0.17,
+                                 "pe_vs_plain40": 0.65,
+                                 "pe_vs_early_stop": 0.46},
+        table=table)
 
 
 if __name__ == "__main__":
