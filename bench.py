@@ -27,11 +27,16 @@ if ROOT not in sys.path:
 METRIC = ("decoded info Mbit/s at N=1024 R=1/2 3.0dB, FER-matched; "
           "PE updates/frame")
 
-# VALU roofline of gfx950 without packed FP32: 256 CUs x 64 lanes x 2.4 GHz
-# 32-bit lane operations per second; eq. (1) costs 12 operations per PE
-# activation (3 adds, 3 magnitude minima, 3 scalings, 3 sign products).
-VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
-OPS_PER_PE = 12
+# FP32 VALU roofline of gfx950 without packed FP32: 256 CUs x 4 SIMDs x 16
+# lanes x 2.4 GHz FP32 lane operations per second (the published FP64 vector
+# rate, 78.6 TFLOP/s, is these lanes at two flops per FMA; the published FP32
+# figure counts packed FP32, which these kernels do not use).  Eq. (1) costs
+# 9 FP32 operations per PE activation: 3 adds, 3 magnitude minima (one median
+# of three each) and 3 scalings.  Its 3 sign products are one 3-input bitwise
+# operation each, which gfx950 issues beside the FP32 work: a chain of
+# median + scaling + bitwise op runs 1.45x the FP32-only lane rate.
+VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
+OPS_PER_PE = 9
 
 # the kernel one step launches (one launch per step)
 KERNEL = "bp_decode_r10_kernel<true, true>"

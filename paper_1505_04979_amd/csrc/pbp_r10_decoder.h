@@ -117,12 +117,34 @@ __host__ __device__ constexpr int lbcol(int c)
     return c == 3 ? 0 : c == 5 ? 1 : c == 7 ? 2 : c == 9 ? 3 : -1;
 }
 
+// LDS word of row r in a boundary column or the transpose buffer.  With rows
+// stored in order, one access of mapping MA puts lanes 4 rows apart (4 lanes
+// per bank), and MC and MD are as strided.  XOR-ing row bits 5, 6 and 7 into
+// the low five bits sends the lanes of every mapping to distinct banks (32
+// lanes at a time, and all 64 over 64 banks).  The map is a bijection on
+// rows 0..2^b - 1 for every b >= 8 and is linear over XOR.
+__host__ __device__ constexpr int swz(int r)
+{
+    return r ^ (((r >> 5) & 1) ? 0x05 : 0) ^ (((r >> 6) & 1) ? 0x1a : 0) ^
+           (((r >> 7) & 1) ? 0x20 : 0);
+}
+
+// address bits that the lane part of a mapping's rows can reach under swz
+__host__ __device__ constexpr int swz_lane_bits(int mp)
+{
+    int m = 0;
+    for (int lb = 0; lb < 6; lb++)
+        m |= swz(1 << lrow(mp, lb));
+    return m;
+}
+
 template <bool FRZ, bool ES>
 struct Decoder {
     const Params &P;
     Smem &S;
     const int lane;
     int lr[4];            // row bits contributed by this lane, per mapping
+    int sl[4];            // swz(lr[mp]): the lane part of an LDS word
     float ch[Q];          // channel LLRs (MA) for the next stage 1, reloaded
                           // from device memory each iteration
     float L2[Q], L4[Q], L6[Q], L8[Q], L10[Q];
@@ -173,6 +195,7 @@ struct Decoder {
                 if ((lane >> lb) & 1)
                     r |= 1 << lrow(mp, lb);
             lr[mp] = r;
+            sl[mp] = swz(r);
         }
 #pragma unroll
         for (int h = 0; h < 2; h++) {
@@ -186,6 +209,18 @@ struct Decoder {
 
     template <int MP>
     __device__ __forceinline__ int row(int q) const { return lr[MP] + rowq(MP, q); }
+
+    // LDS word swz(row) of register q in mapping MP, within the first WMASK+1
+    // words.  swz(row) = sl ^ swz(rowq); the part of swz(rowq) outside the
+    // lane part's bits adds without carries, so it becomes an instruction
+    // offset, and only the part inside (two register bits' worth) needs a XOR.
+    template <int MP, int WMASK = N - 1>
+    __device__ __forceinline__ int lds_word(int q) const
+    {
+        const int c = swz(rowq(MP, q));
+        const int in = c & swz_lane_bits(MP);
+        return (sl[MP] ^ in) + (c & ~swz_lane_bits(MP) & WMASK);
+    }
 
     // largest row offset a lane contributes in mapping mp
     static constexpr int lanemax(int mp)
@@ -272,11 +307,11 @@ struct Decoder {
         for (int h = 0; h < 2; h++) {
 #pragma unroll
             for (int q = h * 8; q < h * 8 + 8; q++)
-                S.tb[row<A>(q) & (N / 2 - 1)] = R[q];
+                S.tb[lds_word<A, N / 2 - 1>(q)] = R[q];
             wave_sync();
 #pragma unroll
             for (int q = h * 8; q < h * 8 + 8; q++)
-                R[q] = S.tb[row<Bm>(q) & (N / 2 - 1)];
+                R[q] = S.tb[lds_word<Bm, N / 2 - 1>(q)];
             wave_sync();
         }
     }
@@ -313,8 +348,8 @@ struct Decoder {
                 X[QB] = ballot(Rb + lbv < 0.0f);
             }
         } else if constexpr (lbcol(J) >= 0) {
-            S.lb[lbcol(J)][row<MP>(QA)] = la;
-            S.lb[lbcol(J)][row<MP>(QB)] = lbv;
+            S.lb[lbcol(J)][lds_word<MP>(QA)] = la;
+            S.lb[lbcol(J)][lds_word<MP>(QB)] = lbv;
         } else {
             float *Lout = lreg<J>();
             Lout[QA] = la;
@@ -399,7 +434,7 @@ struct Decoder {
         constexpr int MP = smap(J);
 #pragma unroll
         for (int q = 0; q < Q; q++)
-            Lt[q] = S.lb[lbcol(J + 1)][row<MP>(q)];
+            Lt[q] = S.lb[lbcol(J + 1)][lds_word<MP>(q)];
     }
 
     // ---- CSFG freezing walk at stage J (Section III, eqs. (2)-(4)) ----
@@ -493,7 +528,7 @@ struct Decoder {
         for (int q = 0; q < Q; q++) {
             if ((q & FM) == T && mine) {
                 if constexpr (lbcol(J + 1) >= 0)
-                    S.lb[lbcol(J + 1)][row<MP>(q)] =
+                    S.lb[lbcol(J + 1)][lds_word<MP>(q)] =
                         check_input<J>(q) < 0.0f ? -kInf : kInf;
                 S.dec[row<MP>(q)] = (uint8_t)((W[q] >> lane) & 1);
             }
