@@ -155,6 +155,7 @@ struct Decoder {
     int l11lo, l11hi;     // rows that may be frozen at stage 10 and read
     int walking;
     int64_t pe;
+    int pskip;            // PEs of this sweep below the frozen prefixes
     // frozen mask as per-lane bits: bit 16 (mp & 1) + q of fzb[mp >> 1] says
     // whether the row of register q in mapping mp is frozen on this lane
     // (two registers, so the checks need no scalar loads and their waits)
@@ -168,14 +169,10 @@ struct Decoder {
         return reinterpret_cast<const_u64_ptr>(base)[mp * Q + q];
     }
 
-    // this lane's frozen bit of register q in mapping mp (laundered at the
-    // point of use, so that ballots of it are not hoisted out of the
-    // iteration loop into long-lived scalar registers)
+    // this lane's frozen bit of register q in mapping mp
     __device__ __forceinline__ bool fzbit(int mp, int q) const
     {
-        uint32_t v = fzb[mp >> 1];
-        asm volatile("" : "+v"(v));
-        return (v >> ((mp & 1) * 16 + q)) & 1;
+        return (fzb[mp >> 1] >> ((mp & 1) * 16 + q)) & 1;
     }
 
     // frozen ballot word [mapping mp][register q] (bit l: lane l's row)
@@ -420,11 +417,14 @@ struct Decoder {
         }
     }
 
+    // stage J runs (N - f) / 2 PEs: N / 2 less the prefix's f / 2, which is
+    // summed per iteration in 32 bits (at most M N / 2 a sweep)
     template <int J>
     __device__ __forceinline__ void stage(int f)
     {
         stage_pes<J>(f);
-        pe += (N - f) >> 1;
+        if constexpr (FRZ && J > 1)
+            pskip += p[J - 1] << (M - J);
     }
 
     // the boundary column L at column J+1 (J even, J < 10) into Lt
@@ -752,6 +752,7 @@ struct Decoder {
         int t = 1;
         for (; t <= P.max_iter; t++) {
             walking = 1;
+            pskip = 0;
             step<1>();
             step<2>();
             transpose_r<MA, MB>();
@@ -767,6 +768,7 @@ struct Decoder {
             load_channel(frame);        // for the next iteration's stage 1
             step<9>();
             step<10>();
+            pe += M * N / 2 - pskip;
             if (decide())
                 break;
         }
