@@ -576,6 +576,31 @@ struct Decoder {
         }
     }
 
+    // lane bits whose row bit is below the stage's block size
+    template <int J>
+    static constexpr int free_lanes()
+    {
+        int n = 0;
+        for (int lb = 0; lb < 6; lb++)
+            if (lrow(smap(J), lb) < M - J)
+                n++;
+        return n;
+    }
+
+    // the lane bits of fixed row bits are the top ones, with consecutive rows
+    template <int J>
+    static constexpr bool fixed_lanes_top()
+    {
+        const int nf = free_lanes<J>();
+        for (int lb = 0; lb < 6; lb++) {
+            if ((lb < nf) != (lrow(smap(J), lb) < M - J))
+                return false;
+            if (lb > nf && lrow(smap(J), lb) != lrow(smap(J), nf) + (lb - nf))
+                return false;
+        }
+        return true;
+    }
+
     // check CSFG k of stage J (and freeze it on success)
     template <int J>
     __device__ __forceinline__ bool check_k(int k)
@@ -583,13 +608,15 @@ struct Decoder {
         constexpr int MP = smap(J);
         constexpr int SH = M - J;          // row bits below SH are free
         constexpr int FM = fixed_qmask<J>();
-        // lanes inside block k
+        // lanes inside block k.  In every stage's mapping the lane bits of
+        // the fixed row bits are the top NF.. 5 and carry consecutive row
+        // bits, so the block's lanes are one run of 2^NF lanes.
+        constexpr int NF = free_lanes<J>();
+        static_assert(fixed_lanes_top<J>(), "block lanes must form one run");
         uint64_t lm = ~0ull;
-#pragma unroll
-        for (int lb = 0; lb < 6; lb++) {
-            const int rb = lrow(MP, lb);
-            if (rb >= SH)
-                lm &= ((k >> (rb - SH)) & 1) ? kLaneSet[lb] : lane_clr(lb);
+        if constexpr (NF < 6) {
+            const int v = (k >> (lrow(MP, NF) - SH)) & ((1 << (6 - NF)) - 1);
+            lm = (NF == 0 ? 1ull : ((1ull << (1 << NF)) - 1)) << (v << NF);
         }
         // fixed register bits of block k
         int t = 0;
