@@ -14,8 +14,10 @@ namespace {
 
 using namespace pbp::generic;
 
+// At m = 14 the working column (64 KB of LDS) leaves room for two groups per
+// compute unit, so each group may take twice the registers.
 template <int M, bool GSTATE>
-__global__ __launch_bounds__(256, 4) void bp_decode_kernel(DecodeParams P)
+__global__ __launch_bounds__(256, M >= 14 ? 2 : 4) void bp_decode_kernel(DecodeParams P)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     float *gslot = GSTATE ? P.state + (int64_t)blockIdx.x * P.state_stride

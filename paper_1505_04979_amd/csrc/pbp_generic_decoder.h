@@ -75,6 +75,33 @@ constexpr int kMaxWordsPerLane = 4;
 // and the stop test on memory latency).
 constexpr int kBatch = 8;
 
+// Groups of four PEs per thread whose 16-byte loads are issued together in
+// the vector sweep.
+constexpr int kBatch4 = 4;
+
+__device__ __forceinline__ float4 ld4(const float *p)
+{
+    return *reinterpret_cast<const float4 *>(p);
+}
+
+__device__ __forceinline__ void st4(float *p, float4 v)
+{
+    *reinterpret_cast<float4 *>(p) = v;
+}
+
+// one PE of eq. (1): inputs L_a, L_b (column j+1), R_a, R_b (column j)
+__device__ __forceinline__ void pe_eq1(float La, float Lb, float Ra, float Rb,
+                                       float alpha, float &oLa, float &oLb,
+                                       float &oRa, float &oRb)
+{
+    const float sm = Lb + Rb;
+    const float g1 = gmin(La, Ra, alpha);
+    oLa = gmin(La, sm, alpha);
+    oLb = Lb + g1;
+    oRa = gmin(Ra, sm, alpha);
+    oRb = Rb + g1;
+}
+
 // In-register F^{(x)s} transform of nw words (nw a power of two, word w =
 // lane + 64 q held in r[q]); each word already transformed internally.
 __device__ __forceinline__ void ffx_cross(uint64_t (&r)[kMaxWordsPerLane],
@@ -116,8 +143,9 @@ struct DecodeParams {
     int64_t state_stride;  // floats per workgroup slot
 };
 
-// Control words kept in LDS.
-struct Ctl {
+// Control words kept in LDS (16-byte aligned size, so the float columns after
+// it take 16-byte accesses).
+struct alignas(16) Ctl {
     int p[16];        // p[j]: number of frozen CSFGs at stage j (p[0] = 0)
     int walking;      // the walk may still check in this sweep
     int bad;          // the last check failed
@@ -212,6 +240,7 @@ __device__ __forceinline__ void decode_frame(const DecodeParams &P,
 
     const float *llr = P.llr + frame * N;
     const float *ch = STATE != 0 ? llr : chl;
+    const bool ch_aligned = (reinterpret_cast<uintptr_t>(ch) & 15) == 0;
     // ---- initial messages ----
     for (int i = tid; i < N; i += NT) {
         if (STATE == 0)
@@ -239,6 +268,15 @@ __device__ __forceinline__ void decode_frame(const DecodeParams &P,
             const int f = ctl->p[j - 1] << (s + 1);  // frozen rows, column j
             float *Lj = Lc(j);
             const float *Lj1 = Lc(j + 1);
+            // The walk's first check of this stage starts on the last word of
+            // its block (below); its L inputs (column j+1, which the sweep
+            // does not write) are loaded now, so the latency overlaps the
+            // sweep.
+            const int pj0 = max(ctl->p[j], 2 * ctl->p[j - 1]);
+            const int hl = h < 64 ? h : 64;      // rows of the last word
+            float lpre = 0.0f;
+            if (P.freezing && P.freeze_input && pj0 < (1 << j) && lane < hl)
+                lpre = Lj1[(pj0 << s) + h - hl + lane];
             // ---- PE updates, eq. (1) ----
             // kBatch PEs per thread at a time: all their loads are issued
             // before any of their stores (which may alias as far as the
@@ -276,24 +314,112 @@ __device__ __forceinline__ void decode_frame(const DecodeParams &P,
                     }
                 }
             };
-            if (j == 1)
-                sweep(ch);
-            else
-                sweep(Rw);
+            // h >= 4: four consecutive PEs per thread, rows a..a+3 and
+            // b..b+3 each one 16-byte access (columns are 16-byte aligned;
+            // the caller's channel column may not be)
+            auto sweep4 = [&](const float *Rin) {
+#pragma unroll 1
+                for (int g0 = (f >> 3) + tid; g0 < N / 8; g0 += kBatch4 * NT) {
+                    float4 La[kBatch4], Lb[kBatch4], Ra[kBatch4], Rb[kBatch4];
+                    int ia[kBatch4];
+#pragma unroll
+                    for (int u = 0; u < kBatch4; u++) {
+                        const int q = 4 * (g0 + u * NT);
+                        const int a = ((q >> s) << (s + 1)) | (q & (h - 1));
+                        ia[u] = a;
+                        if (g0 + u * NT < N / 8) {
+                            La[u] = ld4(Lj1 + a);
+                            Lb[u] = ld4(Lj1 + a + h);
+                            Ra[u] = ld4(Rin + a);
+                            Rb[u] = ld4(Rin + a + h);
+                        }
+                    }
+#pragma unroll
+                    for (int u = 0; u < kBatch4; u++) {
+                        if (g0 + u * NT < N / 8) {
+                            const int a = ia[u], b = a + h;
+                            float4 oLa, oLb, oRa, oRb;
+                            pe_eq1(La[u].x, Lb[u].x, Ra[u].x, Rb[u].x, alpha,
+                                   oLa.x, oLb.x, oRa.x, oRb.x);
+                            pe_eq1(La[u].y, Lb[u].y, Ra[u].y, Rb[u].y, alpha,
+                                   oLa.y, oLb.y, oRa.y, oRb.y);
+                            pe_eq1(La[u].z, Lb[u].z, Ra[u].z, Rb[u].z, alpha,
+                                   oLa.z, oLb.z, oRa.z, oRb.z);
+                            pe_eq1(La[u].w, Lb[u].w, Ra[u].w, Rb[u].w, alpha,
+                                   oLa.w, oLb.w, oRa.w, oRb.w);
+                            st4(Lj + a, oLa);
+                            st4(Lj + b, oLb);
+                            st4(Rw + a, oRa);
+                            st4(Rw + b, oRb);
+                        }
+                    }
+                }
+            };
+            if (j > 1) {
+                if (h >= 4)
+                    sweep4(Rw);
+                else
+                    sweep(Rw);
+            } else {
+                if (h >= 4 && ch_aligned)
+                    sweep4(ch);
+                else
+                    sweep(ch);
+            }
             pe += (N - f) >> 1;
             sync_stage<WAVE, STATE>();
             if (!P.freezing)
                 continue;
             // ---- CSFG freezing walk (Section III) ----
-            // The ballots of a check and the freeze writes are shared out
-            // over the group's wavefronts; wavefront 0 transforms and tests.
+            // Each check first tests the block's last word: its positions
+            // have every higher in-block row bit set, so eq. (3) maps that
+            // word onto itself, and a frozen 1 there fails the block.  Every
+            // wavefront computes this test alike (no barrier); when the block
+            // is one word (h <= 64) it is the whole check.  Otherwise the
+            // full check follows: its ballots and the freeze writes are
+            // shared out over the group's wavefronts, and wavefront 0
+            // transforms and tests.
             {
-                int pj = max(ctl->p[j], 2 * ctl->p[j - 1]);
+                int pj = pj0;
                 int walking = ctl->walking;
                 float *L1 = Lc(j + 1);
                 const int nw = h >= 64 ? h >> 6 : 1;
                 while (pj < (1 << j) && (P.freeze_walk != 0 || walking)) {
                     const int r0 = pj << s;
+                    {
+                        const int rl = r0 + h - hl;      // first row of the word
+                        float v = 0.0f;
+                        if (lane < hl) {
+                            const float lv = pj == pj0 ? lpre : L1[rl + lane];
+                            v = P.freeze_input ? Rw[rl + lane] + lv : Rw[rl + lane];
+                        }
+                        const uint64_t xl = __ballot(v < 0.0f);
+                        const uint64_t ul = ffx_word(xl);
+                        const uint64_t fz =
+                            h >= 64 ? P.frozen_words[rl >> 6]
+                                    : (P.frozen_words[r0 >> 6] >> (r0 & 63)) &
+                                          ((1ull << h) - 1);
+                        if (ul & fz)
+                            break;
+                        if (h <= 64) {
+                            // passed: keep uhat, L at column j+1 := (-1)^xhat inf
+                            if (tid < h)
+                                L1[r0 + tid] = ((xl >> tid) & 1) ? -kInf : kInf;
+                            if (tid == 0) {
+                                const uint64_t msk = (h == 64 ? ~0ull : ((1ull << h) - 1))
+                                                     << (r0 & 63);
+                                dw[r0 >> 6] = (dw[r0 >> 6] & ~msk) | (ul << (r0 & 63));
+                            }
+                            pj++;
+                            if (P.freeze_walk == 0) {
+                                walking = 0;
+                                break;
+                            }
+                            if (P.freeze_walk == 1)
+                                break;
+                            continue;
+                        }
+                    }
                     // eq. (2): hard decisions of the CSFG's inputs, the
                     // loads of kBatch words in flight before their ballots
 #pragma unroll 1

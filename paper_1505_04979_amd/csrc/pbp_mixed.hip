@@ -149,8 +149,9 @@ __global__ __launch_bounds__(64, 2) void class_kernel(ClassParams P)
 // workgroup's device slot, the working R column in LDS).
 constexpr int kWgThreads = 256;
 
+// at m = 14 two groups fit a compute unit's LDS, as in the batch kernel
 template <int M>
-__global__ __launch_bounds__(kWgThreads, 4) void class_wg_kernel(ClassParams P)
+__global__ __launch_bounds__(kWgThreads, M >= 14 ? 2 : 4) void class_wg_kernel(ClassParams P)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ int s_q;
