@@ -193,16 +193,18 @@ def test_rejects_bad_arguments(env):
     assert o["info"].shape == (0, 32)
 
 
-def test_unaligned_buffers_take_the_generic_kernel(env):
-    """N = 1024 LLRs at an address that is not 16-byte aligned are decoded by
-    the generic kernel, with the same results."""
+@pytest.mark.parametrize("N,K,B", [(256, 128, 40), (1024, 512, 40),
+                                   (4096, 2048, 6)])
+def test_unaligned_buffers_take_the_generic_kernel(env, N, K, B):
+    """LLRs at an address that is not 16-byte aligned: N = 1024 is decoded by
+    the generic kernel, and the generic kernel's first stage reads them one
+    PE at a time instead of in 16-byte groups, with the same results."""
     pbp, torch = env
-    N, K = 1024, 512
     fz = frozen_mask(N, K)
-    u, x, llr = make_frames(N, K, 40, 2.5, stream=83)
+    u, x, llr = make_frames(N, K, B, 2.5, stream=83)
     code = code_of(pbp, N, K)
-    buf = torch.zeros(40 * N + 1, dtype=torch.float32, device="cuda")
-    view = buf[1:].view(40, N)
+    buf = torch.zeros(B * N + 1, dtype=torch.float32, device="cuda")
+    view = buf[1:].view(B, N)
     view.copy_(torch.from_numpy(llr))
     assert view.data_ptr() % 16 != 0
     kw = MODES["es_frz_total"]
