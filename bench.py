@@ -40,10 +40,23 @@ OPS_PER_PE = 9
 
 # the kernel one step launches (one launch per step)
 KERNEL = "bp_decode_r10_kernel<true, true>"
-# sources of that kernel (the traffic record is valid while they are unchanged)
-KERNEL_SRCS = [os.path.join(ROOT, "paper_1505_04979_amd", "csrc", f)
-               for f in ("pbp_r10.hip", "pbp_r10_decoder.h", "pbp_r10.h")]
-TRAFFIC = os.path.join(ROOT, "profiles", "traffic_bp_decode_r10_n1024_3db.txt")
+
+# Measured HBM traffic of a workload's roofline kernel: the profile summary
+# that records it, and the kernel's sources (a record is valid while they
+# are unchanged).
+def _csrc(*names):
+    return [os.path.join(ROOT, "paper_1505_04979_amd", "csrc", f) for f in names]
+
+
+TRAFFIC_RECORDS = {
+    "n1024": ("traffic_bp_decode_r10_n1024_3db.txt",
+              _csrc("pbp_r10.hip", "pbp_r10_decoder.h", "pbp_r10.h")),
+    "n16384": ("traffic_bp_decode_n16384_2db.txt",
+               _csrc("pbp_decode.hip", "pbp_generic_decoder.h")),
+    "unrolled": ("traffic_unrolled_backward_n1024.txt",
+                 _csrc("pbp_unrolled.hip")),
+}
+KERNEL_SRCS = TRAFFIC_RECORDS["n1024"][1]
 
 MODES = {
     "es_frz": dict(early_stop=True, freezing=True, freeze_input=1, freeze_walk=0),
@@ -93,30 +106,31 @@ def time_mode(pbp, torch, code, d_llr, opts, steps, warmup):
     return ms, wall, {k: v.cpu().numpy() for k, v in out.items()}
 
 
-def source_digest():
+def source_digest(srcs=None):
     import hashlib
     h = hashlib.sha256()
-    for src in KERNEL_SRCS:
+    for src in srcs or KERNEL_SRCS:
         with open(src, "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:16]
 
 
-def measured_traffic():
-    """HBM bytes per launch of the timed kernel from the FETCH_SIZE and
-    WRITE_SIZE counter runs recorded in the profile summary, scaled by what
-    the same counters read for a plain copy of known size; None when the
-    kernel source has changed since the counters were taken."""
+def measured_traffic(workload="n1024"):
+    """HBM bytes per launch of a workload's roofline kernel from the
+    FETCH_SIZE and WRITE_SIZE counter runs recorded in its profile summary,
+    scaled by what the same counters read for a plain copy of known size;
+    None when the kernel source has changed since the counters were taken."""
+    name, srcs = TRAFFIC_RECORDS[workload]
     vals = {}
     try:
-        with open(TRAFFIC) as f:
+        with open(os.path.join(ROOT, "profiles", name)) as f:
             for ln in f:
                 if ln.startswith("@") and "=" in ln:
                     k, v = ln[1:].split("=", 1)
                     vals[k.strip()] = v.strip()
     except OSError:
         return None
-    if vals.get("source_sha256_16") != source_digest():
+    if vals.get("source_sha256_16") != source_digest(srcs):
         return None
     try:
         return float(vals["traffic_bytes_per_launch"])
@@ -356,7 +370,8 @@ def bench_long_code(args, pbp, torch):
         pe_per_frame=round(float(pe.mean()), 1), fer=errs / B,
         roofline={"bound": "hbm", "achieved": round(gbs, 1),
                   "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                  "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None,
+                  "frac": round(gbs / HBM_PEAK_GBS, 4),
+                  "traffic": measured_traffic("n16384"),
                   "kernel": "bp_decode_kernel<14, true>",
                   "kernel_ms": round(ms, 4)},
         valu={"achieved": round(ops, 3), "peak": round(VALU_PEAK_TOPS, 3),
@@ -523,7 +538,8 @@ def bench_unrolled(args, pbp, torch):
         forward_ms=round(fwd_ms, 4), backward_ms=round(bwd_ms, 4),
         roofline={"bound": "hbm", "achieved": round(bwd_gbs, 1),
                   "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                  "frac": round(bwd_gbs / HBM_PEAK_GBS, 4), "traffic": None,
+                  "frac": round(bwd_gbs / HBM_PEAK_GBS, 4),
+                  "traffic": measured_traffic("unrolled"),
                   "kernel": "unrolled_backward_kernel<10>",
                   "kernel_ms": round(bwd_ms, 4),
                   "note": "checkpoint reads (T x B x (m-1) x N x 4 B), LLR "
