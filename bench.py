@@ -243,9 +243,9 @@ def main():
     res = {}
     for name in (["es_frz"] if args.no_reference_modes else ["es_frz", "es", "plain"]):
         opts = dict(MODES[name], max_iter=max_iter, alpha=alpha)
-        steps = args.steps if name == "es_frz" else max(1, args.steps // 3)
+        steps = args.steps
         ms, wall, out = time_mode(pbp, torch, code, d_llr, opts, steps,
-                                  args.warmup if name == "es_frz" else 1)
+                                  args.warmup)
         errs = int(np.sum(np.any(out["info"] != info, axis=1)))
         res[name] = dict(ms=ms, wall=wall, steps=steps, errors=errs,
                          fer=errs / B, iters=float(out["iters"].mean()),
