@@ -231,11 +231,19 @@ __global__ void clear_kernel(int *cnt, int n)
         cnt[threadIdx.x] = 0;
 }
 
+// Bucket counts: each workgroup counts its frames in LDS, then adds one total
+// per bucket to the device counts (one frame one device atomic would queue
+// every frame of the batch on the same few counters).
 __global__ void count_kernel(CodeSet cs, const int32_t *code_of_frame,
                              const int64_t *llr_off, const float *llr,
                              int32_t B, int *cnt, int32_t *iters_out,
                              int64_t *pe_out)
 {
+    __shared__ int h[kMaxCodes + 1];
+    const int nb = cs.ncodes + 1;
+    for (int i = threadIdx.x; i < nb; i += blockDim.x)
+        h[i] = 0;
+    __syncthreads();
     for (int f = blockIdx.x * blockDim.x + threadIdx.x; f < B;
          f += gridDim.x * blockDim.x) {
         const int b = bucket_of(cs, code_of_frame, llr_off, llr, f);
@@ -244,8 +252,12 @@ __global__ void count_kernel(CodeSet cs, const int32_t *code_of_frame,
             if (pe_out)
                 pe_out[f] = 0;
         }
-        atomicAdd(&cnt[b], 1);
+        atomicAdd(&h[b], 1);
     }
+    __syncthreads();
+    for (int i = threadIdx.x; i < nb; i += blockDim.x)
+        if (h[i])
+            atomicAdd(&cnt[i], h[i]);
 }
 
 // bounds[b] := start of bucket b (exclusive prefix of the counts), with
@@ -263,14 +275,35 @@ __global__ void scan_kernel(const int *cnt, int nb, int *bounds, int *cursor)
     }
 }
 
+// Frames into their buckets, one block of frames at a time: ranks within the
+// block from LDS counters, then one device atomic per bucket reserves the
+// block's range.  Frames of a bucket end up in no fixed order (nothing
+// depends on it: each frame's results are its own).
 __global__ void scatter_kernel(CodeSet cs, const int32_t *code_of_frame,
                                const int64_t *llr_off, const float *llr,
                                int32_t B, int *cursor, int32_t *order)
 {
-    for (int f = blockIdx.x * blockDim.x + threadIdx.x; f < B;
-         f += gridDim.x * blockDim.x) {
-        const int b = bucket_of(cs, code_of_frame, llr_off, llr, f);
-        order[atomicAdd(&cursor[b], 1)] = f;
+    __shared__ int h[kMaxCodes + 1];
+    __shared__ int base[kMaxCodes + 1];
+    const int nb = cs.ncodes + 1;
+    for (int64_t f0 = (int64_t)blockIdx.x * blockDim.x; f0 < B;
+         f0 += (int64_t)gridDim.x * blockDim.x) {
+        for (int i = threadIdx.x; i < nb; i += blockDim.x)
+            h[i] = 0;
+        __syncthreads();
+        const int64_t f = f0 + threadIdx.x;
+        int b = 0, r = 0;
+        if (f < B) {
+            b = bucket_of(cs, code_of_frame, llr_off, llr, (int)f);
+            r = atomicAdd(&h[b], 1);
+        }
+        __syncthreads();
+        for (int i = threadIdx.x; i < nb; i += blockDim.x)
+            base[i] = h[i] ? atomicAdd(&cursor[i], h[i]) : 0;
+        __syncthreads();
+        if (f < B)
+            order[base[b] + r] = (int32_t)f;
+        __syncthreads();
     }
 }
 
