@@ -229,3 +229,41 @@ def test_long_code_batch_sampled_parity(env):
     r = oracle.decode(llr[idx], fz, max_iter=60, soft=True, **kw)
     sub = {k: v[idx] for k, v in g.items()}
     assert_parity(sub, r, K, fz)
+
+
+@pytest.mark.parametrize("N,K,B", [(1024, 512, 96), (2048, 1024, 24)])
+def test_graph_capture_replays(env, N, K, B):
+    """pbp_decode captured once in a graph and replayed on new LLRs (copied
+    into the captured buffer between replays) matches eager calls and the
+    oracle, replay after replay: the persistent kernel's frame counter and
+    the long-code state slots are left ready for the next launch."""
+    pbp, torch = env
+    print(f"[parity] graph replay N={N} B={B}", flush=True)
+    fz = frozen_mask(N, K)
+    code = code_of(pbp, N, K)
+    kw = MODES["es_frz_total"]
+    u, x, llr0 = make_frames(N, K, B, 2.5, stream=97)
+    static_llr = torch.from_numpy(llr0).cuda()
+    out = pbp.pbp_decode(code, static_llr, soft=True, **kw)
+    torch.cuda.synchronize()
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        pbp.pbp_decode(code, static_llr, soft=True, out=out, stream=s, **kw)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        pbp.pbp_decode(code, static_llr, soft=True, out=out, stream=s, **kw)
+    torch.cuda.synchronize()
+    for rep in range(4):
+        _, _, llr = make_frames(N, K, B, 2.0 + 0.5 * rep, stream=98 + rep)
+        static_llr.copy_(torch.from_numpy(llr))
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        got = {k: v.cpu().numpy() for k, v in out.items()}
+        eager = gpu_decode(env, N, K, llr, **kw)
+        for k in got:
+            assert np.array_equal(got[k], eager[k]), (rep, k)
+        idx = np.arange(0, B, max(1, B // 6))
+        r = oracle.decode(llr[idx], fz, soft=True, **kw)
+        assert_parity({k: v[idx] for k, v in got.items()}, r, K, fz)
