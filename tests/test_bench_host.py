@@ -44,8 +44,12 @@ def test_traffic_is_reported_only_while_the_sources_match(tmp_path,
     monkeypatch.setitem(bench.TRAFFIC_RECORDS, "t", (str(rec), [str(src)]))
     digest = bench.source_digest([str(src)])
     rec.write_text(f"# summary\n@source_sha256_16 = {digest}\n"
+                   "@frames_per_launch = 64\n"
                    "@traffic_bytes_per_launch = 12345\n")
     assert bench.measured_traffic("t") == 12345.0
+    assert bench.measured_traffic("t", 64) == 12345.0
+    # counted at another batch size: not this launch's traffic
+    assert bench.measured_traffic("t", 65) is None
     src.write_text("// kernel v2\n")
     assert bench.measured_traffic("t") is None
     rec.unlink()
