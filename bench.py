@@ -615,6 +615,7 @@ def bench_sweep(args, pbp, torch):
                          "mbps": round(B * K / ms / 1e3, 1)}
         table.append(row)
         del d_llr
+        print(f"[sweep] {eb} dB done", file=sys.stderr, flush=True)
     at3 = next(r for r in table if r["ebn0_db"] == 3.0)
     base, es, fz = at3["plain40"], at3["early_stop"], at3["es_freeze_total"]
     ctx = {"iterations_vs_plain40": round(1 - fz["avg_iters"] / base["avg_iters"], 4),
