@@ -73,13 +73,14 @@ def wilson(k, n, z):
     return c - h, c + h
 
 
-def make_inputs(pbp, torch, code, frozen, N, K, B, ebn0, stream,
-                chunk=1 << 17):
+def make_inputs(pbp, torch, code, frozen, N, K, B, ebn0, stream, chunk=None):
     """Seeded info bits and noise (host), encoding on the device, channel
     LLRs (host, FP64 rounded once), uploaded to device memory.  The noise
     and LLRs are made a chunk of frames at a time (the draws are counter-based
     per frame, so chunking does not change them)."""
     import synth
+    if chunk is None:
+        chunk = max(1, (1 << 27) // N)      # 1 GB of FP64 noise at a time
     info = synth.info_bits(K, B, stream=stream)
     d_info = torch.from_numpy(info).cuda()
     cw = pbp.pbp_encode(code, d_info)
@@ -358,14 +359,14 @@ def bench_long_code(args, pbp, torch):
     written; plus the channel LLRs once per iteration)."""
     N, K, max_iter, alpha = 16384, 8192, 60, 0.9375
     ebn0 = 2.0 if args.ebn0 is None else args.ebn0
-    B = args.batch or 4096
+    B = args.batch or 10 ** 5      # the long-code workload's frame count
     frozen = pbp.pbp_construct(N, K, 0.0)
     code = pbp.Code(N, K, frozen)
     info, d_llr = make_inputs(pbp, torch, code, frozen, N, K, B, ebn0,
                               stream=(5 << 16) + 1)
     opts = dict(MODES["es_frz"], max_iter=max_iter, alpha=alpha)
     out = pbp.pbp_decode(code, d_llr, **opts)
-    steps = max(1, args.steps // 2)
+    steps = max(1, args.steps // 3)
     ms = _timed(torch, lambda: pbp.pbp_decode(code, d_llr, out=out, **opts),
                 steps, 1)
     iters = out["iters"].cpu().numpy().astype(np.float64)

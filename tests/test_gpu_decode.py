@@ -233,17 +233,30 @@ def test_unaligned_buffers_take_the_generic_kernel(env, N, K, B):
 
 def test_long_code_batch_sampled_parity(env):
     """The long-code benchmark's launch shape ((16384, 8192) code, 2.0 dB,
-    4096 frames, 60 iterations, early stop + freezing), checked on sampled
-    frames."""
-    N, K, B = 16384, 8192, 4096
-    print(f"[parity] long batch N={N} B={B}", flush=True)
-    fz = frozen_mask(N, K)
-    u, x, llr = make_frames(N, K, B, 2.0, stream=2025)
+    10^5 frames in one launch, 60 iterations, early stop + freezing),
+    checked on sampled frames; inputs made a chunk of frames at a time."""
+    pbp, torch = env
+    N, K, B, chunk = 16384, 8192, 10 ** 5, 1 << 13
     kw = MODES["es_frz_total"]
-    g = gpu_decode(env, N, K, llr, max_iter=60, **kw)
-    idx = np.random.default_rng(1).choice(B, 3, replace=False)
-    r = oracle.decode(llr[idx], fz, max_iter=60, soft=True, **kw)
-    sub = {k: v[idx] for k, v in g.items()}
+    fz = frozen_mask(N, K)
+    code = code_of(pbp, N, K)
+    idx = np.sort(np.random.default_rng(1).choice(B, 3, replace=False))
+    llr_s = np.empty((len(idx), N), np.float32)
+    d_llr = torch.empty((B, N), dtype=torch.float32, device="cuda")
+    for lo in range(0, B, chunk):
+        hi = min(B, lo + chunk)
+        _, _, llr = make_frames(N, K, hi - lo, 2.0, stream=2025, frame0=lo,
+                                frozen=fz)
+        d_llr[lo:hi].copy_(torch.from_numpy(llr))
+        sel = (idx >= lo) & (idx < hi)
+        llr_s[sel] = llr[idx[sel] - lo]
+    print(f"[parity] long batch N={N} B={B}", flush=True)
+    o = pbp.pbp_decode(code, d_llr, max_iter=60, soft=True, **kw)
+    torch.cuda.synchronize()
+    ti = torch.from_numpy(idx).cuda()
+    sub = {k: v[ti].cpu().numpy() for k, v in o.items()}
+    del d_llr, o
+    r = oracle.decode(llr_s, fz, max_iter=60, soft=True, **kw)
     assert_parity(sub, r, K, fz)
 
 
