@@ -498,15 +498,47 @@ def bench_mixed(args, pbp, torch):
         input_generation_s=round(gen_s, 2), tune_s=round(tune_s, 2))
 
 
+def _training_step_ms(pbp, torch, N, K, T, B, steps, stream):
+    """Time one training step (forward, BCE, backward, SGD update) of the
+    unrolled decoder on a fresh batch of the (N, K) code."""
+    import synth
+    m = N.bit_length() - 1
+    frozen = pbp.pbp_construct(N, K, 0.0)
+    code = pbp.Code(N, K, frozen)
+    ebn0 = 1.0 + 3.0 * synth.uniform(B, stream=stream, word=1)
+    info = synth.info_bits(K, B, stream=stream)
+    cw = pbp.pbp_encode(code, torch.from_numpy(info).cuda()).cpu().numpy()
+    llr = synth.channel_llr(cw, synth.normals(N, B, stream=stream), ebn0,
+                            K / N)
+    d_llr = torch.from_numpy(llr).cuda()
+    info_pos = torch.from_numpy(np.flatnonzero(frozen == 0)).cuda()
+    u_info = torch.from_numpy(info.astype(np.float32)).cuda()
+    alpha = torch.full((T, m, 2), 0.9375, dtype=torch.float32, device="cuda",
+                       requires_grad=True)
+    opt = torch.optim.SGD([alpha], lr=0.01)
+
+    def step():
+        opt.zero_grad(set_to_none=False)
+        loss = pbp.info_bce(pbp.unrolled_bp(d_llr, alpha, code), u_info,
+                            info_pos)
+        loss.backward()
+        opt.step()
+
+    return _timed(torch, step, steps, 2)
+
+
 def bench_unrolled(args, pbp, torch):
     """One training step of the unrolled decoder: (1024, 512) code, T = 20,
     4096 frames at Eb/N0 uniform in [1, 4] dB: forward with checkpoints,
-    BCE of the information bits, backward to the 400 scales."""
+    BCE of the information bits, backward to the 400 scales.  The (128, 64)
+    code's step is timed beside it."""
     import synth
     N, K, T = 1024, 512, 20
     m = 10
     B = args.batch or 4096
     stream = (4 << 16) + 1
+    ms128 = _training_step_ms(pbp, torch, 128, 64, T, B, max(1, args.steps),
+                              (4 << 16) + 2)
     frozen = pbp.pbp_construct(N, K, 0.0)
     code = pbp.Code(N, K, frozen)
     ebn0 = 1.0 + 3.0 * synth.uniform(B, stream=stream, word=1)
@@ -553,6 +585,9 @@ def bench_unrolled(args, pbp, torch):
                      "400 scales, 4096 frames, Eb/N0 U[1,4] dB",
          "N": N, "K": K, "T": T, "frames_per_step": B},
         forward_ms=round(fwd_ms, 4), backward_ms=round(bwd_ms, 4),
+        n128_training_step={"ms_per_step": round(ms128, 4),
+                            "frames_per_s": round(B / ms128 * 1e3, 1),
+                            "code": [128, 64], "T": T, "frames_per_step": B},
         roofline={"bound": "hbm", "achieved": round(bwd_gbs, 1),
                   "peak": HBM_PEAK_GBS, "unit": "GB/s",
                   "frac": round(bwd_gbs / HBM_PEAK_GBS, 4),

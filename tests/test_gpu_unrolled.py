@@ -163,13 +163,15 @@ def test_training_steps_reduce_the_loss(env):
     assert losses[-1] < losses[0]
 
 
-def test_training_batch_shape_sampled(env):
-    """The training configuration (N = 1024, T = 20, 4096 frames, Eb/N0
-    uniform in [1, 4] dB): outputs and per-frame scale gradients of sampled
-    frames against the oracle, and the frame sum."""
+@pytest.mark.parametrize("N,K", [(128, 64), (1024, 512)])
+def test_training_batch_shape_sampled(env, N, K):
+    """The training configurations (N = 128 and 1024, T = 20, 4096 frames,
+    Eb/N0 uniform in [1, 4] dB): outputs and per-frame scale gradients of
+    sampled frames against the oracle, and the frame sum."""
     pbp, torch = env
-    N, K, T, B = 1024, 512, 20, 4096
-    m = 10
+    T, B = 20, 4096
+    m = N.bit_length() - 1
+    print(f"[unrolled] training batch N={N} B={B}", flush=True)
     fz = frozen_mask(N, K)
     ebn0 = np.random.default_rng(7).uniform(1.0, 4.0, size=B)
     u, _, llr = make_frames(N, K, B, ebn0, stream=91)
