@@ -55,6 +55,10 @@ TRAFFIC_RECORDS = {
                _csrc("pbp_decode.hip", "pbp_generic_decoder.h")),
     "unrolled": ("traffic_unrolled_backward_n1024.txt",
                  _csrc("pbp_unrolled.hip")),
+    # the mixed batch's N = 4096 frames decoded alone: three class kernels
+    # (one per rate) per decode, summed
+    "mixed": ("traffic_class_wg_n4096_mixed.txt",
+              _csrc("pbp_mixed.hip", "pbp_generic_decoder.h")),
 }
 KERNEL_SRCS = TRAFFIC_RECORDS["n1024"][1]
 
@@ -486,7 +490,8 @@ def bench_mixed(args, pbp, torch):
         pe_per_frame=round(float(pe.mean()), 1), fer=errs / B,
         roofline={"bound": "hbm", "achieved": round(long_gbs, 1),
                   "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                  "frac": round(long_gbs / HBM_PEAK_GBS, 4), "traffic": None,
+                  "frac": round(long_gbs / HBM_PEAK_GBS, 4),
+                  "traffic": measured_traffic("mixed", B),
                   "kernel": "class_wg_kernel<12> (the three N = 4096 codes)",
                   "kernel_ms": round(ms_long, 4),
                   "note": "16 B per active PE (L state in device memory) "
