@@ -109,16 +109,25 @@ def time_mode(pbp, torch, code, d_llr, opts, steps, warmup):
         pbp.pbp_decode(code, d_llr, out=out, **opts)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
-    ev0.record()
-    for _ in range(steps):
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+    evs[0].record()
+    for i in range(steps):
         pbp.pbp_decode(code, d_llr, out=out, **opts)
-    ev1.record()
+        evs[i + 1].record()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    ms = ev0.elapsed_time(ev1) / steps
-    return ms, wall, {k: v.cpu().numpy() for k, v in out.items()}
+    ms = evs[0].elapsed_time(evs[-1]) / steps
+    per_step = sorted(evs[i].elapsed_time(evs[i + 1]) for i in range(steps))
+    median = per_step[steps // 2] if steps % 2 else \
+        0.5 * (per_step[steps // 2 - 1] + per_step[steps // 2])
+    # end to end: one more decode plus the copy of its decided bits and
+    # iteration counts to the host
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    pbp.pbp_decode(code, d_llr, out=out, **opts)
+    host = {k: v.cpu().numpy() for k, v in out.items()}
+    e2e = (time.perf_counter() - t1) * 1e3
+    return ms, wall, host, median, e2e
 
 
 def source_digest(srcs=None):
@@ -207,6 +216,62 @@ def cpu_baseline(llr, frozen, info_ref, opts, K, seconds):
             "frames": frames, "gpu_mismatches": mism}
 
 
+def _oracle_all(llr, frozen, opts, threads, chunk=256):
+    """The oracle over every frame of llr (host FP32 array), in chunks on a
+    thread pool; returns the concatenated info bits, iterations and PE
+    counts."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    import oracle
+    B = len(llr)
+    parts = {}
+
+    def job(lo):
+        parts[lo] = oracle.decode(llr[lo:lo + chunk], frozen, **opts)
+        return lo
+
+    with ThreadPoolExecutor(threads) as ex:
+        done = 0
+        for _ in ex.map(job, range(0, B, chunk)):
+            done += 1
+            if done % 512 == 0:
+                print(f"[parity] {min(B, done * chunk)} / {B} frames",
+                      file=sys.stderr, flush=True)
+    keys = sorted(parts)
+    return {k: np.concatenate([parts[lo][k] for lo in keys])
+            for k in ("info", "iters", "pe")}
+
+
+def full_parity(d_llr, frozen, info_ref, res, K):
+    """Every frame of the timed batch through the FP32 oracle in each mode
+    (bits, iterations and PE counts against the GPU's, frame by frame), and
+    through the FP64 oracle in the headline mode (the GPU's error rate
+    against the FP64 oracle's 95% interval)."""
+    threads = max(1, min(16, os.cpu_count() or 1))
+    llr = d_llr.cpu().numpy()
+    B = len(llr)
+    out = {"frames": B, "threads": threads}
+    t0 = time.perf_counter()
+    for name, r in res.items():
+        print(f"[parity] mode {name}: FP32 oracle on {B} frames",
+              file=sys.stderr, flush=True)
+        o = _oracle_all(llr, frozen, r["opts"], threads)
+        g = r["out"]
+        bad = (np.any(o["info"] != g["info"], axis=1) |
+               (o["iters"] != g["iters"]) | (o["pe"] != g["pe"]))
+        out[name] = {"mismatched_frames": int(bad.sum())}
+    h = res["es_frz"]
+    print(f"[parity] FP64 oracle on {B} frames", file=sys.stderr, flush=True)
+    o64 = _oracle_all(llr, frozen, dict(h["opts"], prec="f64"), threads)
+    e64 = int(np.sum(np.any(o64["info"] != info_ref, axis=1)))
+    lo, hi = wilson(e64, B, 1.959963984540054)
+    out["fp64_es_frz"] = {"fer": e64 / B, "fer_ci95": [lo, hi],
+                          "gpu_fer": h["fer"],
+                          "gpu_inside": bool(lo <= h["fer"] <= hi)}
+    out["seconds"] = round(time.perf_counter() - t0, 1)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -219,6 +284,11 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-reference-modes", action="store_true")
+    ap.add_argument("--full-parity", action="store_true",
+                    help="also decode every frame of the batch with the FP32 "
+                         "oracle in each mode (bits, iterations and PE "
+                         "counts compared) and with the FP64 oracle in the "
+                         "headline mode (error-rate interval); takes minutes")
     ap.add_argument("--workload", default="n1024",
                     choices=["n1024", "n16384", "mixed", "unrolled", "sweep"],
                     help="n1024: the headline line (default); n16384: the "
@@ -263,13 +333,14 @@ def main():
     for name in (["es_frz"] if args.no_reference_modes else ["es_frz", "es", "plain"]):
         opts = dict(MODES[name], max_iter=max_iter, alpha=alpha)
         steps = args.steps
-        ms, wall, out = time_mode(pbp, torch, code, d_llr, opts, steps,
-                                  args.warmup)
+        ms, wall, out, med, e2e = time_mode(pbp, torch, code, d_llr, opts,
+                                            steps, args.warmup)
         errs = int(np.sum(np.any(out["info"] != info, axis=1)))
         res[name] = dict(ms=ms, wall=wall, steps=steps, errors=errs,
                          fer=errs / B, iters=float(out["iters"].mean()),
                          pe=float(out["pe"].mean()),
-                         mbps=B * K / (ms / 1e3) / 1e6, info=out["info"])
+                         mbps=B * K / (ms / 1e3) / 1e6, info=out["info"],
+                         median_ms=med, e2e_ms=e2e, out=out, opts=opts)
 
     h = res["es_frz"]
     line = {
@@ -294,6 +365,9 @@ def main():
         "pe_per_frame": round(h["pe"], 1),
         "avg_iters": round(h["iters"], 3),
         "fer": h["fer"],
+        "ms_per_step_median": round(h["median_ms"], 4),
+        # one decode plus the copy of its bits and iteration counts to the host
+        "end_to_end_ms": round(h["e2e_ms"], 3),
     }
     pe_total = h["pe"] * B
     achieved = OPS_PER_PE * pe_total / (h["ms"] / 1e3) / 1e12
@@ -321,6 +395,8 @@ def main():
         opts = dict(MODES["es_frz"], max_iter=max_iter, alpha=alpha)
         line["cpu_baseline"] = cpu_baseline(d_host, frozen, h["info"], opts, K,
                                             args.cpu_seconds)
+    if args.full_parity:
+        line["full_parity"] = full_parity(d_llr, frozen, info, res, K)
     line["input_generation_s"] = round(gen_s, 2)
     print(json.dumps(line), flush=True)
 
