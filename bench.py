@@ -177,13 +177,22 @@ def copy_calibration(torch, nbytes, reps):
                       "launches": reps}), flush=True)
 
 
-def cpu_baseline(llr, frozen, info_ref, opts, K, seconds):
+def _oracle_frozen(N, K):
+    """The frozen set of the oracle's own construction (the oracle's inputs
+    come from the oracle and the seeded draws, not from the library)."""
+    import oracle
+    fz, _ = oracle.construct(N, K, 0.0)
+    return np.array(fz, dtype=np.uint8)
+
+
+def cpu_baseline(llr, K, info_ref, opts, seconds):
     """The FP32 oracle on the host's cores over a bounded sample of the same
     frames, in chunks, until the time budget is spent."""
     import threading
     from concurrent.futures import ThreadPoolExecutor
 
     import oracle
+    frozen = _oracle_frozen(llr.shape[1], K)
     threads = max(1, min(16, os.cpu_count() or 1))
     chunk = 16
     nxt = [0]
@@ -242,14 +251,22 @@ def _oracle_all(llr, frozen, opts, threads, chunk=256):
             for k in ("info", "iters", "pe")}
 
 
-def full_parity(d_llr, frozen, info_ref, res, K):
+def _compare(o, info, iters, pe):
+    """Frames where the oracle's outputs o differ from the given GPU outputs
+    in information bits, iteration count or PE count."""
+    return int(np.sum(np.any(o["info"] != info, axis=1) |
+                      (o["iters"] != iters) | (o["pe"] != pe)))
+
+
+def full_parity(d_llr, info_ref, res, K):
     """Every frame of the timed batch through the FP32 oracle in each mode
     (bits, iterations and PE counts against the GPU's, frame by frame), and
     through the FP64 oracle in the headline mode (the GPU's error rate
-    against the FP64 oracle's 95% interval)."""
+    against the FP64 oracle's 95% interval).  Part of the CPU baseline leg."""
     threads = max(1, min(16, os.cpu_count() or 1))
     llr = d_llr.cpu().numpy()
     B = len(llr)
+    frozen = _oracle_frozen(llr.shape[1], K)
     out = {"frames": B, "threads": threads}
     t0 = time.perf_counter()
     for name, r in res.items():
@@ -393,10 +410,11 @@ def main():
         # in its time budget
         d_host = d_llr[:min(B, 1 << 19)].cpu().numpy()
         opts = dict(MODES["es_frz"], max_iter=max_iter, alpha=alpha)
-        line["cpu_baseline"] = cpu_baseline(d_host, frozen, h["info"], opts, K,
+        line["cpu_baseline"] = cpu_baseline(d_host, K, h["info"], opts,
                                             args.cpu_seconds)
-    if args.full_parity:
-        line["full_parity"] = full_parity(d_llr, frozen, info, res, K)
+        if args.full_parity:
+            line["cpu_baseline"]["full_parity"] = full_parity(d_llr, info,
+                                                              res, K)
     line["input_generation_s"] = round(gen_s, 2)
     print(json.dumps(line), flush=True)
 
@@ -452,6 +470,26 @@ def bench_long_code(args, pbp, torch):
     iters = out["iters"].cpu().numpy().astype(np.float64)
     pe = out["pe"].cpu().numpy().astype(np.float64)
     errs = int(np.sum(np.any(out["info"].cpu().numpy() != info, axis=1)))
+    extra = {}
+    if args.full_parity:
+        # CPU baseline leg: the first 10^4 frames of the batch through the
+        # FP32 oracle, timed, and compared frame by frame
+        S = min(B, 10 ** 4)
+        threads = max(1, min(16, os.cpu_count() or 1))
+        print(f"[parity] long code: FP32 oracle on {S} frames", file=sys.stderr,
+              flush=True)
+        t0 = time.perf_counter()
+        o = _oracle_all(d_llr[:S].cpu().numpy(), _oracle_frozen(N, K), opts,
+                        threads, chunk=16)
+        wall = time.perf_counter() - t0
+        extra["cpu_baseline"] = {
+            "value": round(S * K / wall / 1e6, 3), "unit": "Mbit/s",
+            "cores": threads, "kind": "oracle",
+            "sample": f"the first {S} frames of the batch, FP32 oracle, "
+                      f"{threads} threads, {wall:.1f} s",
+            "frames": S, "gpu_mismatches": _compare(
+                o, out["info"][:S].cpu().numpy(),
+                out["iters"][:S].cpu().numpy(), out["pe"][:S].cpu().numpy())}
     alg_bytes = 16.0 * pe.sum() + 4.0 * N * iters.sum() + B * (K + 12)
     gbs = alg_bytes / (ms / 1e3) / 1e9
     ops = OPS_PER_PE * pe.sum() / (ms / 1e3) / 1e12
@@ -472,7 +510,8 @@ def bench_long_code(args, pbp, torch):
                   "kernel": "bp_decode_kernel<14, true>",
                   "kernel_ms": round(ms, 4)},
         valu={"achieved": round(ops, 3), "peak": round(VALU_PEAK_TOPS, 3),
-              "unit": "TOP/s", "frac": round(ops / VALU_PEAK_TOPS, 4)})
+              "unit": "TOP/s", "frac": round(ops / VALU_PEAK_TOPS, 4)},
+        **extra)
 
 
 def bench_mixed(args, pbp, torch):
@@ -531,9 +570,41 @@ def bench_mixed(args, pbp, torch):
     ms = _timed(torch, lambda: pbp.pbp_decode_mixed(
         plan, d_cof, d_lo, d_io, d_llr, opts=opts, out=out), steps, 1)
     fill = pbp.pbp_mixed_plan_fill(plan)
-    pe = out["pe"].cpu().numpy().astype(np.float64)
+    pe_i = out["pe"].cpu().numpy()
+    pe = pe_i.astype(np.float64)
     iters = out["iters"].cpu().numpy()
     bits = out["info"].cpu().numpy()
+    extra = {}
+    if args.full_parity:
+        # CPU baseline leg: a seeded sample of 10^4 frames of the batch
+        # through the FP32 oracle, code by code, timed and compared frame by
+        # frame
+        S = min(B, 10 ** 4)
+        samp = np.sort(np.random.default_rng(2).choice(B, S, replace=False))
+        threads = max(1, min(16, os.cpu_count() or 1))
+        print(f"[parity] mixed: FP32 oracle on {S} sampled frames",
+              file=sys.stderr, flush=True)
+        t0 = time.perf_counter()
+        bad = 0
+        for c, (N, K) in enumerate(dims):
+            fs = samp[cof[samp] == c]
+            if len(fs) == 0:
+                continue
+            pos = torch.from_numpy(llr_off[fs]).cuda()[:, None] + \
+                torch.arange(N, device="cuda")[None, :]
+            llr_c = d_llr[pos.reshape(-1)].reshape(len(fs), N).cpu().numpy()
+            o = _oracle_all(llr_c, _oracle_frozen(N, K),
+                            dict(MODES["es_frz"], max_iter=60, alpha=0.9375),
+                            threads, chunk=16)
+            got = bits[info_off[fs][:, None] + np.arange(K)[None, :]]
+            bad += _compare(o, got, iters[fs], pe_i[fs])
+        wall = time.perf_counter() - t0
+        extra["cpu_baseline"] = {
+            "value": round(float(Ks[samp].sum()) / wall / 1e6, 3),
+            "unit": "Mbit/s", "cores": threads, "kind": "oracle",
+            "sample": f"{S} seeded frames of the batch, FP32 oracle, "
+                      f"{threads} threads, {wall:.1f} s",
+            "frames": S, "gpu_mismatches": bad}
     errs = 0
     for c, (idx, info) in info_ref.items():
         K = dims[c][1]
@@ -576,7 +647,8 @@ def bench_mixed(args, pbp, torch):
         step_valu={"achieved": round(ops, 3),
                    "peak": round(VALU_PEAK_TOPS, 3), "unit": "TOP/s",
                    "frac": round(ops / VALU_PEAK_TOPS, 4)},
-        input_generation_s=round(gen_s, 2), tune_s=round(tune_s, 2))
+        input_generation_s=round(gen_s, 2), tune_s=round(tune_s, 2),
+        **extra)
 
 
 def _training_step_ms(pbp, torch, N, K, T, B, steps, stream):
@@ -711,6 +783,7 @@ def bench_sweep(args, pbp, torch):
     frozen = pbp.pbp_construct(N, K, 0.0)
     code = pbp.Code(N, K, frozen)
     points = [1.0, 1.5, 2.0, 2.5, 3.0, 3.5]
+    fz_oracle = _oracle_frozen(N, K) if args.full_parity else None
     table = []
     total_ms = 0.0
     for k, eb in enumerate(points):
@@ -730,6 +803,19 @@ def bench_sweep(args, pbp, torch):
                          "avg_iters": round(float(out["iters"].float().mean()), 3),
                          "pe_per_frame": round(float(out["pe"].double().mean()), 1),
                          "mbps": round(B * K / ms / 1e3, 1)}
+            if args.full_parity and name in ("plain40", "early_stop",
+                                             "es_freeze_total"):
+                # CPU baseline leg: the first 10^5 frames of the point
+                # through the FP32 oracle, compared frame by frame
+                S = min(B, 10 ** 5)
+                print(f"[parity] {eb} dB {name}: FP32 oracle on {S} frames",
+                      file=sys.stderr, flush=True)
+                o = _oracle_all(d_llr[:S].cpu().numpy(), fz_oracle, opts,
+                                max(1, min(16, os.cpu_count() or 1)))
+                row[name]["oracle_frames"] = S
+                row[name]["oracle_mismatched_frames"] = _compare(
+                    o, out["info"][:S].cpu().numpy(),
+                    out["iters"][:S].cpu().numpy(), out["pe"][:S].cpu().numpy())
         table.append(row)
         del d_llr
         print(f"[sweep] {eb} dB done", file=sys.stderr, flush=True)
