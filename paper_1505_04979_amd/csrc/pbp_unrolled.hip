@@ -196,14 +196,16 @@ __device__ __forceinline__ void sync_lds()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
 
-// Backward pass.  L^{t-1} is read straight from the checkpoint of
-// iteration t (device memory, mostly in L2), and the adjoint of L^{t-1} is
-// written over it: stage j reads rows a, b of column j+1 and then, in the
-// same thread, replaces them with their adjoints, which iteration t-1 reads.
-// LDS holds only R^t (columns 1..m) and two columns of its adjoint, so two
-// workgroups fit on a compute unit.
+// Backward pass.  L^{t-1} is read once from the checkpoint of iteration t
+// (device memory), by the recompute of the R sweep, and kept in registers
+// for the adjoint stages; the adjoint of L^{t-1} is written over the
+// checkpoint: stage j replaces rows a, b of column j+1 (read by this thread
+// only) with their adjoints, which iteration t-1 reads.  LDS holds only R^t
+// (columns 1..m) and two columns of its adjoint (about 49 KB at m = 10), and
+// at most 80 VGPRs keep six wavefronts per SIMD, so three groups of eight
+// wavefronts fit on a compute unit.
 template <int M>
-__global__ __launch_bounds__(Shape<M>::NT, 4) void unrolled_backward_kernel(BwdParams P)
+__global__ __launch_bounds__(Shape<M>::NT, 6) void unrolled_backward_kernel(BwdParams P)
 {
     using S = Shape<M>;
     constexpr int N = S::N, H = S::H, NT = S::NT, NW = S::NW;
@@ -243,14 +245,21 @@ __global__ __launch_bounds__(Shape<M>::NT, 4) void unrolled_backward_kernel(BwdP
                     Rc[i] = yv[k];
             }
             sync_lds();
-            // rows of this thread's PE at stage j
+            // rows of this thread's PE at stage j, from a copy of the thread
+            // index made opaque per iteration: the rows and offsets of all
+            // stages would otherwise be kept in registers across iterations
+            int tt = tid;
+            asm volatile("" : "+v"(tt));
             auto row_a = [&](int j) {
                 const int sh = M - j;
-                return ((tid >> sh) << (sh + 1)) | (tid & ((1 << sh) - 1));
+                return ((tt >> sh) << (sh + 1)) | (tt & ((1 << sh) - 1));
             };
             // the R sweep of iteration t+1; each stage's L^{t-1} inputs are
-            // requested one stage ahead, so their latency overlaps a stage
+            // requested one stage ahead, so their latency overlaps a stage,
+            // and are kept for the adjoint stages (one read of the
+            // checkpoint per iteration)
             float pLa = 0.0f, pLb = 0.0f;
+            float keepLa[M], keepLb[M];
             if (tid < H && M > 1) {
                 const int a = row_a(1);
                 pLa = lprev(2, a);
@@ -266,6 +275,8 @@ __global__ __launch_bounds__(Shape<M>::NT, 4) void unrolled_backward_kernel(BwdP
                     const float *Ri = Rc + (j - 1) * N;
                     float *Ro = Rc + j * N;
                     const float La = pLa, Lb = pLb;
+                    keepLa[j - 1] = La;
+                    keepLb[j - 1] = Lb;
                     if (j + 1 < M) {
                         const int an = row_a(j + 1);
                         pLa = lprev(j + 2, an);
@@ -288,16 +299,11 @@ __global__ __launch_bounds__(Shape<M>::NT, 4) void unrolled_backward_kernel(BwdP
                 }
             }
             sync_lds();
-            // this thread's share of the scale gradients, per stage; reduced
-            // over the group once per iteration, off the stages' critical path
-            float accL[M], accR[M];
-            // the inputs from device memory of stage j (L^{t-1} at column
-            // j+1 and the adjoint of L^t at column j), one stage ahead
-            float qLa = 0.0f, qLb = 0.0f, qiLa = 0.0f, qiLb = 0.0f;
+            // the input from device memory of stage j (the adjoint of L^t at
+            // column j), one stage ahead
+            float qiLa = 0.0f, qiLb = 0.0f;
             auto fetch = [&](int j) {
                 const int a = row_a(j), b = a + (1 << (M - j));
-                qLa = lprev(j + 1, a);
-                qLb = lprev(j + 1, b);
                 qiLa = 0.0f;
                 qiLb = 0.0f;
                 if (j >= 2 && dk) {
@@ -319,7 +325,10 @@ __global__ __launch_bounds__(Shape<M>::NT, 4) void unrolled_backward_kernel(BwdP
                     const float *Ri = Rc + (j - 1) * N;
                     const float *dRi = dR + ((j + 1) & 1) * N;   // column j+1
                     float *dRo = dR + (j & 1) * N;               // column j
-                    const float La = qLa, Lb = qLb;
+                    // L^{t-1} at column j+1: kept from the R sweep, or the
+                    // frozen prior at column m+1
+                    const float La = j < M ? keepLa[j - 1] : lprev(M + 1, a);
+                    const float Lb = j < M ? keepLb[j - 1] : lprev(M + 1, b);
                     const float iLa = qiLa, iLb = qiLb;
                     float oLa = 0.0f, oLb = 0.0f;
                     // stage j-1 reads column j, which this stage leaves as is
@@ -363,21 +372,21 @@ __global__ __launch_bounds__(Shape<M>::NT, 4) void unrolled_backward_kernel(BwdP
                     dRo[a] = dRa;
                     dRo[b] = dRb;
                 }
-                accL[j - 1] = daL;
-                accR[j - 1] = daR;
+                // this stage's scale gradients, summed over the wavefront
+                // (the group's sum is taken once per iteration); the shuffles
+                // overlap the next stage's load in flight
+                {
+                    float vL = daL, vR = daR;
+                    for (int o = 32; o >= 1; o >>= 1) {
+                        vL += __shfl_xor(vL, o, 64);
+                        vR += __shfl_xor(vR, o, 64);
+                    }
+                    if (lane == 0) {
+                        red[((j - 1) * NW + wv) * 2] = vL;
+                        red[((j - 1) * NW + wv) * 2 + 1] = vR;
+                    }
+                }
                 sync_lds();
-            }
-#pragma unroll
-            for (int k = 0; k < M; k++) {
-                float vL = accL[k], vR = accR[k];
-                for (int o = 32; o >= 1; o >>= 1) {
-                    vL += __shfl_xor(vL, o, 64);
-                    vR += __shfl_xor(vR, o, 64);
-                }
-                if (lane == 0) {
-                    red[(k * NW + wv) * 2] = vL;
-                    red[(k * NW + wv) * 2 + 1] = vR;
-                }
             }
 #pragma unroll
             for (int k = 0; k < S::YR; k++) {
@@ -460,7 +469,7 @@ hipError_t launch_backward(const pbp_code *c, BwdParams &P, hipStream_t st)
                                        (int)lds);
     if (e != hipSuccess)
         return e;
-    hipLaunchKernelGGL(kern, dim3((unsigned)frames_grid(c, P.B, 2)),
+    hipLaunchKernelGGL(kern, dim3((unsigned)frames_grid(c, P.B, 3)),
                        dim3(Shape<M>::NT), lds, st, P);
     return hipGetLastError();
 }
