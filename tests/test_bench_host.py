@@ -68,3 +68,17 @@ def test_committed_records_parse():
                 for ln in open(path) if ln.startswith("@")}
         assert {"source_sha256_16", "traffic_bytes_per_launch",
                 "fetch_scale", "write_scale"} <= keys, name
+
+
+def test_committed_records_match_the_kernel_sources():
+    """Each traffic record was counted on the kernel sources as they stand,
+    so the benchmark line carries it (a kernel change needs a new count)."""
+    for name, (record, srcs) in bench.TRAFFIC_RECORDS.items():
+        path = os.path.join(ROOT, "profiles", record)
+        assert os.path.exists(path), name
+        lines = {ln[1:].split("=", 1)[0].strip(): ln.split("=", 1)[1].strip()
+                 for ln in open(path) if ln.startswith("@")}
+        assert lines["source_sha256_16"] == bench.source_digest(srcs), name
+        frames = int(lines["frames_per_launch"])
+        assert bench.measured_traffic(name, frames) == float(
+            lines["traffic_bytes_per_launch"]), name
