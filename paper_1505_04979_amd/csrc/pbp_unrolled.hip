@@ -119,6 +119,36 @@ size_t bwd_lds_bytes()
     return sizeof(float) * ((size_t)(M + 2) * S::N + (size_t)M * S::NW * 2);
 }
 
+// Barrier that orders LDS only (device-memory accesses of a stage are
+// ordered by the full barrier that ends each iteration).
+__device__ __forceinline__ void sync_lds()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+// LDS ordering between two consecutive stages.  With one thread per PE, the
+// PEs of wavefront w at a stage whose offset is at most 64 all lie in rows
+// [128 w, 128 w + 128); when both stages have such offsets (or the group is
+// one wavefront) every LDS word the second stage touches was last touched by
+// the same wavefront, so ordering within the wavefront is enough.
+__device__ __forceinline__ void sync_wave_lds()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront", "local");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront", "local");
+}
+
+template <int NW>
+__device__ __forceinline__ void sync_stages(int h_first, int h_second)
+{
+    if (NW == 1 || (h_first <= 64 && h_second <= 64))
+        sync_wave_lds();
+    else
+        sync_lds();
+}
+
 template <int M>
 __global__ __launch_bounds__(Shape<M>::NT) void unrolled_forward_kernel(FwdParams P)
 {
@@ -178,7 +208,10 @@ __global__ __launch_bounds__(Shape<M>::NT) void unrolled_forward_kernel(FwdParam
                     Ro[a] = aR * g0(Ra, s);
                     Ro[b] = Rb + aR * g1;
                 }
-                __syncthreads();
+                if (j < M)
+                    sync_stages<S::NW>(h, h >> 1);
+                else
+                    __syncthreads();
             }
         }
         for (int i = tid; i < N; i += NT)
@@ -187,14 +220,6 @@ __global__ __launch_bounds__(Shape<M>::NT) void unrolled_forward_kernel(FwdParam
     }
 }
 
-// Barrier that orders LDS only (device-memory accesses of a stage are
-// ordered by the full barrier that ends each iteration).
-__device__ __forceinline__ void sync_lds()
-{
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
-    __builtin_amdgcn_s_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
-}
 
 // Backward pass.  L^{t-1} is read once from the checkpoint of iteration t
 // (device memory), by the recompute of the R sweep, and kept in registers
@@ -287,7 +312,7 @@ __global__ __launch_bounds__(Shape<M>::NT, 6) void unrolled_backward_kernel(BwdP
                     Ro[a] = aR * g0(Ra, s);
                     Ro[b] = Rb + aR * g0(La, Ra);
                 }
-                sync_lds();
+                sync_stages<NW>(h, h >> 1);
             }
             {
                 float *d = dR + ((M + 1) & 1) * N;
@@ -386,7 +411,12 @@ __global__ __launch_bounds__(Shape<M>::NT, 6) void unrolled_backward_kernel(BwdP
                         red[((j - 1) * NW + wv) * 2 + 1] = vR;
                     }
                 }
-                sync_lds();
+                // after stage 1 the channel gradient is read in another
+                // thread order
+                if (j > 1)
+                    sync_stages<NW>(h, h << 1);
+                else
+                    sync_lds();
             }
 #pragma unroll
             for (int k = 0; k < S::YR; k++) {
