@@ -263,13 +263,6 @@ __global__ __launch_bounds__(Shape<M>::NT, 6) void unrolled_backward_kernel(BwdP
                 return c == M + 1 ? (frozen_at(P.frozen, r) ? kInf : 0.0f)
                                   : ck[(c - 2) * N + r];
             };
-#pragma unroll
-            for (int k = 0; k < S::YR; k++) {
-                const int i = tid + k * NT;
-                if (i < N)
-                    Rc[i] = yv[k];
-            }
-            sync_lds();
             // rows of this thread's PE at stage j, from a copy of the thread
             // index made opaque per iteration: the rows and offsets of all
             // stages would otherwise be kept in registers across iterations
@@ -279,17 +272,27 @@ __global__ __launch_bounds__(Shape<M>::NT, 6) void unrolled_backward_kernel(BwdP
                 const int sh = M - j;
                 return ((tt >> sh) << (sh + 1)) | (tt & ((1 << sh) - 1));
             };
-            // the R sweep of iteration t+1; each stage's L^{t-1} inputs are
-            // requested one stage ahead, so their latency overlaps a stage,
-            // and are kept for the adjoint stages (one read of the
-            // checkpoint per iteration)
-            float pLa = 0.0f, pLb = 0.0f;
+            // L^{t-1} at columns 2..m for the R sweep of iteration t+1, all
+            // requested at once so that their latencies overlap, and kept for
+            // the adjoint stages (one read of the checkpoint per iteration)
             float keepLa[M], keepLb[M];
-            if (tid < H && M > 1) {
-                const int a = row_a(1);
-                pLa = lprev(2, a);
-                pLb = lprev(2, a + (1 << (M - 1)));
+#pragma unroll
+            for (int j = 1; j < M; j++) {
+                keepLa[j - 1] = 0.0f;
+                keepLb[j - 1] = 0.0f;
+                if (tid < H) {
+                    const int a = row_a(j);
+                    keepLa[j - 1] = lprev(j + 1, a);
+                    keepLb[j - 1] = lprev(j + 1, a + (1 << (M - j)));
+                }
             }
+#pragma unroll
+            for (int k = 0; k < S::YR; k++) {
+                const int i = tid + k * NT;
+                if (i < N)
+                    Rc[i] = yv[k];
+            }
+            sync_lds();
 #pragma unroll
             for (int j = 1; j < M; j++) {
                 const float aR = scale_at(P.alpha, ((int64_t)t * M + (j - 1)) * 2 + 1);
@@ -299,14 +302,7 @@ __global__ __launch_bounds__(Shape<M>::NT, 6) void unrolled_backward_kernel(BwdP
                     const int b = a + h;
                     const float *Ri = Rc + (j - 1) * N;
                     float *Ro = Rc + j * N;
-                    const float La = pLa, Lb = pLb;
-                    keepLa[j - 1] = La;
-                    keepLb[j - 1] = Lb;
-                    if (j + 1 < M) {
-                        const int an = row_a(j + 1);
-                        pLa = lprev(j + 2, an);
-                        pLb = lprev(j + 2, an + (h >> 1));
-                    }
+                    const float La = keepLa[j - 1], Lb = keepLb[j - 1];
                     const float Ra = Ri[a], Rb = Ri[b];
                     const float s = Lb + Rb;
                     Ro[a] = aR * g0(Ra, s);
