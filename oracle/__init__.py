@@ -10,8 +10,9 @@ Functions and the passages they follow:
                      recursion for the ranking.
   encode             Section II, Fig. 1 (x = u F^{(x)m}).
   csfg_check         eqs. (2)-(4), Lemma 1.
-  decode             Section II-A eq. (1) and schedule; Section III freezing;
-                     G-matrix stop; Section IV PE count.
+  decode             Section II-A eq. (1) and schedule (single sweep, or the
+                     round trip: an L pass then an R pass); Section III
+                     freezing; G-matrix stop; Section IV PE count.
   unrolled_forward   eq. (1) with per-(iteration, stage, direction) scales.
   unrolled_grad      reverse-mode derivative of unrolled_forward.
 """
@@ -30,12 +31,15 @@ WALK_ONE_PER_STAGE = 1
 WALK_GREEDY = 2
 INPUT_R = 0
 INPUT_TOTAL = 1
+SCHEDULE_SINGLE = 0
+SCHEDULE_ROUND_TRIP = 1
 
 
 class Opts(ctypes.Structure):
     _fields_ = [("max_iter", ctypes.c_int32), ("early_stop", ctypes.c_int32),
                 ("freezing", ctypes.c_int32), ("freeze_input", ctypes.c_int32),
-                ("freeze_walk", ctypes.c_int32), ("alpha", ctypes.c_double)]
+                ("freeze_walk", ctypes.c_int32), ("alpha", ctypes.c_double),
+                ("schedule", ctypes.c_int32)]
 
 
 _libs = {}
@@ -106,7 +110,8 @@ def csfg_check(msgs, frozen, prec="f64"):
 
 def decode(llr, frozen, max_iter=40, early_stop=True, freezing=False,
            freeze_input=INPUT_TOTAL, freeze_walk=WALK_ONE_PER_ITER,
-           alpha=0.9375, prec="f32", soft=False, trace=False, trace_cap=1 << 16):
+           alpha=0.9375, prec="f32", soft=False, trace=False, trace_cap=1 << 16,
+           schedule=SCHEDULE_SINGLE):
     """Decode a batch of FP32 LLRs (B, N).
 
     Returns a dict with ``uhat`` (B, N) source-word decisions, ``info``
@@ -122,7 +127,7 @@ def decode(llr, frozen, max_iter=40, early_stop=True, freezing=False,
     frozen = np.ascontiguousarray(frozen, dtype=np.uint8)
     assert frozen.shape == (N,)
     o = Opts(int(max_iter), int(bool(early_stop)), int(bool(freezing)),
-             int(freeze_input), int(freeze_walk), float(alpha))
+             int(freeze_input), int(freeze_walk), float(alpha), int(schedule))
     uhat = np.empty((B, N), np.uint8)
     iters = np.empty(B, np.int32)
     pe = np.empty(B, np.int64)

@@ -39,6 +39,9 @@ typedef struct {
     int32_t freeze_walk;  /* 0: one freeze per iteration, 1: one per stage,
                              2: greedy (keep checking after a freeze)       */
     double alpha;         /* min-sum scaling (Section IV: 0.9375)           */
+    int32_t schedule;     /* 0: single left-to-right sweep (the reading of
+                             Section II-A), 1: round trip (a right-to-left
+                             pass of L, then a left-to-right pass of R)    */
 } oracle_opts;
 
 enum { WALK_ONE_PER_ITER = 0, WALK_ONE_PER_STAGE = 1, WALK_GREEDY = 2 };
@@ -109,6 +112,10 @@ int oracle_csfg_check(int nlog, const real *in, const uint8_t *frozen,
  * Schedule (Section II-A): per iteration t the PEs are activated stage by
  * stage from left to right; stage j computes L^t at column j from L^{t-1}
  * at column j+1 and R^t at column j, and R^t at column j+1, by eq. (1).
+ * The round trip (schedule 1, no freezing) is the other common reading of
+ * the same equations: per iteration, every L output of eq. (1) for stages
+ * m, m-1, ..., 1, then every R output for stages 1, ..., m; each pass
+ * counts as one activation of every PE.
  * Initial messages: R at column 1 = channel LLRs; L at column m+1 = +inf at
  * frozen rows and 0 at information rows; every other L = 0.
  *
@@ -158,7 +165,40 @@ static int decode_frame(int m, const uint8_t *frozen, const float *llr,
 
     for (t = 1; t <= o->max_iter; t++) {
         int walking = 1;
-        for (int j = 1; j <= m; j++) {
+        if (o->schedule == 1) {
+            /* round trip: eq. (1)'s L outputs for stages m..1 from the L
+             * just computed at column j+1 and the R of the previous pass,
+             * then its R outputs for stages 1..m from the R just computed
+             * at column j and this pass's L at column j+1; every PE is
+             * activated once in each pass */
+            for (int j = m; j >= 1; j--) {
+                const int h = n >> j;
+                for (int a = 0; a < n; a++) {
+                    if (a & h)
+                        continue;
+                    const int b = a + h;
+                    const real La = L[AT(j + 1, a)], Lb = L[AT(j + 1, b)];
+                    const real Ra = R[AT(j, a)], Rb = R[AT(j, b)];
+                    L[AT(j, b)] = Lb + gterm(alpha, La, Ra);
+                    L[AT(j, a)] = gterm(alpha, La, Lb + Rb);
+                    pe++;
+                }
+            }
+            for (int j = 1; j <= m; j++) {
+                const int h = n >> j;
+                for (int a = 0; a < n; a++) {
+                    if (a & h)
+                        continue;
+                    const int b = a + h;
+                    const real La = L[AT(j + 1, a)], Lb = L[AT(j + 1, b)];
+                    const real Ra = R[AT(j, a)], Rb = R[AT(j, b)];
+                    R[AT(j + 1, a)] = gterm(alpha, Ra, Lb + Rb);
+                    R[AT(j + 1, b)] = Rb + gterm(alpha, La, Ra);
+                    pe++;
+                }
+            }
+        }
+        for (int j = 1; j <= m && o->schedule == 0; j++) {
             const int h = n >> j;               /* 2^{m-j} */
             const int f = p[j - 1] * 2 * h;     /* frozen rows at column j */
             for (int a = f; a < n; a++) {
@@ -251,7 +291,8 @@ int oracle_decode(int m, const uint8_t *frozen, int64_t B, const float *llr,
                   int64_t *pe, real *soft, int32_t *trace, int32_t trace_cap,
                   int32_t *trace_len)
 {
-    if (m < 1 || m > 20 || B < 0 || !o || o->max_iter < 1)
+    if (m < 1 || m > 20 || B < 0 || !o || o->max_iter < 1 ||
+        o->schedule < 0 || o->schedule > 1 || (o->schedule == 1 && o->freezing))
         return -1;
     int32_t dummy = 0;
     if (!trace_len)
