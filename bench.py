@@ -307,11 +307,13 @@ def main():
                          "counts compared) and with the FP64 oracle in the "
                          "headline mode (error-rate interval); takes minutes")
     ap.add_argument("--workload", default="n1024",
-                    choices=["n1024", "n16384", "mixed", "unrolled", "sweep"],
+                    choices=["n1024", "n16384", "mixed", "unrolled", "sweep",
+                             "round_trip"],
                     help="n1024: the headline line (default); n16384: the "
                          "long-code decoder; mixed: the mixed-code persistent "
                          "decoder; unrolled: one training step of the "
-                         "unrolled decoder")
+                         "unrolled decoder; round_trip: the round-trip "
+                         "schedule on the headline's frames")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run a plain device copy of BYTES (counter "
                          "yardstick) and exit")
@@ -330,7 +332,8 @@ def main():
         return
     if args.workload != "n1024":
         fn = {"n16384": bench_long_code, "mixed": bench_mixed,
-              "unrolled": bench_unrolled, "sweep": bench_sweep}[args.workload]
+              "unrolled": bench_unrolled, "sweep": bench_sweep,
+              "round_trip": bench_round_trip}[args.workload]
         print(json.dumps(fn(args, pbp, torch)), flush=True)
         return
 
@@ -649,6 +652,70 @@ def bench_mixed(args, pbp, torch):
                    "frac": round(ops / VALU_PEAK_TOPS, 4)},
         input_generation_s=round(gen_s, 2), tune_s=round(tune_s, 2),
         **extra)
+
+
+# FP32 operations per PE activation of one round-trip pass: each pass
+# computes two outputs of eq. (1), each an add, a median and a scaling
+OPS_PER_PE_PASS = 6
+
+
+def bench_round_trip(args, pbp, torch):
+    """The round-trip schedule (an L pass over stages m..1, then an R pass
+    over stages 1..m, per iteration; early stop, no freezing) on the
+    headline's frames: (1024, 512) code, 3.0 dB, 10^6 frames.  The single
+    sweep with early stop is timed on the same frames beside it."""
+    import oracle
+    N, K, B, max_iter, alpha = 1024, 512, args.batch or 10 ** 6, 40, 0.9375
+    frozen = pbp.pbp_construct(N, K, 0.0)
+    code = pbp.Code(N, K, frozen)
+    ebn0 = 3.0 if args.ebn0 is None else args.ebn0
+    info, d_llr = make_inputs(pbp, torch, code, frozen, N, K, B, ebn0,
+                              stream=(2 << 16) + 5)
+    base = dict(early_stop=True, freezing=False, max_iter=max_iter,
+                alpha=alpha)
+    res = {}
+    for name, sched in (("round_trip", "round_trip"), ("single", "single")):
+        ms, _, out, med, _ = time_mode(pbp, torch, code, d_llr,
+                                       dict(base, schedule=sched),
+                                       args.steps, args.warmup)
+        errs = int(np.sum(np.any(out["info"] != info, axis=1)))
+        res[name] = dict(ms=ms, median=med, errors=errs, fer=errs / B,
+                         iters=float(out["iters"].mean()),
+                         pe=float(out["pe"].mean()),
+                         mbps=B * K / (ms / 1e3) / 1e6, info=out["info"])
+    r, s1 = res["round_trip"], res["single"]
+    achieved = OPS_PER_PE_PASS * r["pe"] * B / (r["ms"] / 1e3) / 1e12
+    line = _line(
+        "decoded info Mbit/s at N=1024 R=1/2 3.0dB, round-trip BP schedule "
+        "with early stop", round(r["mbps"], 2), "Mbit/s", args.steps,
+        args.warmup, r["ms"],
+        {"workload": f"polar BP decode, (1024,512) code, BPSK/AWGN Eb/N0 "
+                     f"{ebn0} dB, round-trip schedule, early stop",
+         "N": N, "K": K, "ebn0_db": ebn0, "frames_per_step": B,
+         "max_iter": max_iter, "alpha": alpha},
+        ms_per_step_median=round(r["median"], 4),
+        avg_iters=round(r["iters"], 3), pe_per_frame=round(r["pe"], 1),
+        fer=r["fer"], fer_ci95=list(wilson(r["errors"], B, 1.959963984540054)),
+        single_sweep_early_stop={
+            "mbps": round(s1["mbps"], 2), "ms_per_step": round(s1["ms"], 4),
+            "fer": s1["fer"],
+            "fer_ci95": list(wilson(s1["errors"], B, 1.959963984540054)),
+            "avg_iters": round(s1["iters"], 3),
+            "pe_per_frame": round(s1["pe"], 1)},
+        roofline={"bound": "alu", "achieved": round(achieved, 3),
+                  "peak": round(VALU_PEAK_TOPS, 3), "unit": "TOP/s",
+                  "frac": round(achieved / VALU_PEAK_TOPS, 4),
+                  "traffic": None, "kernel": "bp_round_trip_kernel<10>",
+                  "kernel_ms": round(r["ms"], 4),
+                  "note": "6 FP32 operations per PE activation of one pass, "
+                          "m N activations per iteration"})
+    if not args.no_cpu_baseline:
+        d_host = d_llr[:min(B, 1 << 19)].cpu().numpy()
+        line["cpu_baseline"] = cpu_baseline(
+            d_host, K, r["info"],
+            dict(base, schedule=oracle.SCHEDULE_ROUND_TRIP),
+            args.cpu_seconds)
+    return line
 
 
 def _training_step_ms(pbp, torch, N, K, T, B, steps, stream):

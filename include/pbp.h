@@ -129,6 +129,20 @@ int32_t pbp_decode(const pbp_code *code, const float *llr, int64_t B,
                    int32_t *iters_out, int64_t *pe_out, float *soft_out,
                    void *stream);
 
+/* The round-trip schedule, the other common reading of Section II-A's
+ * schedule (pbp_decode runs the single left-to-right sweep): each iteration
+ * computes every L output of eq. (1) for stages m, m-1, ..., 1 (from the L
+ * just computed at column j+1 and the previous pass's R at column j), then
+ * every R output for stages 1, ..., m (from the R just computed at column j
+ * and this pass's L at column j+1).  Arguments, layouts, ownership and the
+ * stop test as for pbp_decode; pe_out counts both passes, m N PE
+ * activations per iteration.  opts->freezing must be 0 and N <= 1024.
+ * Errors: as pbp_decode; PBP_EUNSUPPORTED for freezing or N > 1024. */
+int32_t pbp_decode_round_trip(const pbp_code *code, const float *llr,
+                              int64_t B, const pbp_decode_opts *opts,
+                              uint8_t *info_out, int32_t *iters_out,
+                              int64_t *pe_out, float *soft_out, void *stream);
+
 /* ---- Mixed-code persistent decoding ----------------------------------
  * One batch may mix codes of different lengths and rates (each frame names
  * its code); the whole batch is decoded by one launch of persistent

@@ -51,6 +51,9 @@ _SIGNATURES = [
     ("pbp_decode", ctypes.c_int32,
      [_P, _P, ctypes.c_int64, ctypes.POINTER(pbp_decode_opts), _P, _P, _P, _P,
       _P]),
+    ("pbp_decode_round_trip", ctypes.c_int32,
+     [_P, _P, ctypes.c_int64, ctypes.POINTER(pbp_decode_opts), _P, _P, _P, _P,
+      _P]),
     ("pbp_mixed_plan_create", ctypes.c_int32,
      [_P, ctypes.c_int32, ctypes.c_int64, ctypes.POINTER(_P)]),
     ("pbp_mixed_plan_destroy", None, [_P]),
@@ -196,13 +199,15 @@ def make_opts(max_iter=40, early_stop=True, freezing=False, freeze_input=1,
 
 
 def pbp_decode(code, llr, opts=None, pe=True, soft=False, out=None,
-               stream=None, **kw):
+               stream=None, schedule="single", **kw):
     """Decode FP32 LLRs (B, N) on the device.
 
     Returns a dict of device tensors: ``info`` (B, K) uint8, ``iters`` (B,)
     int32, ``pe`` (B,) int64 when asked, ``soft`` (B, N) float32 when asked.
     ``opts`` is a pbp_decode_opts or None (then keyword options apply).
     Pass ``out`` (a dict of preallocated tensors) to avoid allocation.
+    ``schedule``: "single" (pbp_decode) or "round_trip"
+    (pbp_decode_round_trip: no freezing, N <= 1024).
     """
     import torch
     if opts is None:
@@ -218,7 +223,10 @@ def pbp_decode(code, llr, opts=None, pe=True, soft=False, out=None,
         o["pe"] = torch.empty((B,), dtype=torch.int64, device=dev)
     if soft and "soft" not in o:
         o["soft"] = torch.empty((B, code.N), dtype=torch.float32, device=dev)
-    _check("pbp_decode", lib().pbp_decode(
+    if schedule not in ("single", "round_trip"):
+        raise ValueError(f"unknown schedule {schedule!r}")
+    name = "pbp_decode" if schedule == "single" else "pbp_decode_round_trip"
+    _check(name, getattr(lib(), name)(
         code.handle, _dev_ptr(llr, torch.float32, (B, code.N), "llr"), B,
         ctypes.byref(opts),
         _dev_ptr(o["info"], torch.uint8, (B, code.K), "info"),
