@@ -96,3 +96,19 @@ def test_pe_count_and_rejected_options():
     assert np.array_equal(o["pe"], o["iters"].astype(np.int64) * 7 * N)
     with pytest.raises(ValueError):
         oracle.decode(llr, frozen, freezing=True, schedule=RT)
+
+
+def test_fp32_and_fp64_agree_statistically():
+    """The FP32 round trip (what the GPU reproduces bit for bit) has its
+    frame error rate inside the FP64 round trip's 95% interval."""
+    from helpers import wilson
+    N, K, B = 256, 128, 3000
+    u, _, llr = make_frames(N, K, B, 2.5, stream=(9 << 16) + 77)
+    fz = frozen_mask(N, K)
+    a = oracle.decode(llr, fz, prec="f32", schedule=RT)
+    b = oracle.decode(llr, fz, prec="f64", schedule=RT)
+    ea = int(np.sum(np.any(a["uhat"] != u, axis=1)))
+    eb = int(np.sum(np.any(b["uhat"] != u, axis=1)))
+    lo, hi = wilson(eb, B)
+    assert lo <= ea / B <= hi
+    assert np.mean(np.all(a["uhat"] == b["uhat"], axis=1)) > 0.97
