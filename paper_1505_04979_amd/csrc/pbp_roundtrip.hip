@@ -93,7 +93,7 @@ struct RtSmem {
 };
 
 template <int M>
-__global__ __launch_bounds__(RtShape<M>::NT, 6) void bp_round_trip_kernel(RtParams P)
+__global__ __launch_bounds__(RtShape<M>::NT, 8) void bp_round_trip_kernel(RtParams P)
 {
     using S = RtShape<M>;
     constexpr int N = S::N, H = S::H, NW = S::NW;
@@ -244,8 +244,8 @@ template <int M>
 hipError_t launch_rt(const pbp_code *c, const RtParams &P, hipStream_t st)
 {
     using S = RtShape<M>;
-    // at most 80 VGPRs: six wavefronts per SIMD, 24 per compute unit
-    const int per_cu = S::NW >= 8 ? 3 : 24 / S::NW;
+    // at most 64 VGPRs: eight wavefronts per SIMD, 32 per compute unit
+    const int per_cu = S::NW >= 8 ? 4 : 32 / S::NW;
     int64_t grid = (int64_t)(c->cus > 0 ? c->cus : 256) * per_cu;
     if (grid > P.B)
         grid = P.B;
