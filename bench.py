@@ -837,6 +837,9 @@ SWEEP_MODES = {
                             freeze_walk=1),
     "es_freeze_greedy": dict(early_stop=True, freezing=True, freeze_input=1,
                              freeze_walk=2),
+    # the round-trip schedule with early stop (pbp_decode_round_trip)
+    "round_trip_es": dict(early_stop=True, freezing=False,
+                          schedule="round_trip"),
 }
 
 
@@ -871,13 +874,18 @@ def bench_sweep(args, pbp, torch):
                          "pe_per_frame": round(float(out["pe"].double().mean()), 1),
                          "mbps": round(B * K / ms / 1e3, 1)}
             if args.full_parity and name in ("plain40", "early_stop",
-                                             "es_freeze_total"):
+                                             "es_freeze_total",
+                                             "round_trip_es"):
                 # CPU baseline leg: the first 10^5 frames of the point
                 # through the FP32 oracle, compared frame by frame
                 S = min(B, 10 ** 5)
                 print(f"[parity] {eb} dB {name}: FP32 oracle on {S} frames",
                       file=sys.stderr, flush=True)
-                o = _oracle_all(d_llr[:S].cpu().numpy(), fz_oracle, opts,
+                oo = dict(opts)
+                if oo.pop("schedule", "single") == "round_trip":
+                    import oracle
+                    oo["schedule"] = oracle.SCHEDULE_ROUND_TRIP
+                o = _oracle_all(d_llr[:S].cpu().numpy(), fz_oracle, oo,
                                 max(1, min(16, os.cpu_count() or 1)))
                 row[name]["oracle_frames"] = S
                 row[name]["oracle_mismatched_frames"] = _compare(
@@ -897,7 +905,8 @@ def bench_sweep(args, pbp, torch):
         "all decoding modes", round(fz["mbps"], 2), "Mbit/s (3.0 dB, early "
         "stop + freezing)", 1, 0, total_ms,
         {"workload": "(1024,512) code, Eb/N0 1.0-3.5 dB, "
-                     f"{B} frames per point, 7 modes on the same LLRs",
+                     f"{B} frames per point, {len(SWEEP_MODES)} modes on "
+                     "the same LLRs",
          "frames_per_point": B, "max_iter": max_iter, "alpha": alpha},
         reductions_at_3db=ctx,
         paper_reductions_at_3db={"iterations_vs_plain40": 0.46,
