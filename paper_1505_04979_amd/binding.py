@@ -238,6 +238,15 @@ def pbp_decode(code, llr, opts=None, pe=True, soft=False, out=None,
     return o
 
 
+def pbp_decode_round_trip(code, llr, opts=None, pe=True, soft=False, out=None,
+                          stream=None, **kw):
+    """pbp_decode with the round-trip schedule (the C entry point
+    pbp_decode_round_trip): same arguments and outputs; no freezing,
+    N <= 1024."""
+    return pbp_decode(code, llr, opts=opts, pe=pe, soft=soft, out=out,
+                      stream=stream, schedule="round_trip", **kw)
+
+
 def pbp_unrolled_forward(code, llr, alpha, ckpt=True, out=None, stream=None):
     """Unrolled BP with scales ``alpha`` (T, m, 2) float32 on the device.
 

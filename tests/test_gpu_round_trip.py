@@ -43,8 +43,8 @@ def run_both(env, N, K, llr, frozen=None, max_iter=40, alpha=0.9375,
     fz = frozen_mask(N, K) if frozen is None else frozen
     code = code_of(pbp, N, K, frozen)
     d = torch.from_numpy(llr).cuda()
-    g = pbp.pbp_decode(code, d, max_iter=max_iter, alpha=alpha,
-                       early_stop=early_stop, soft=True, schedule="round_trip")
+    g = pbp.pbp_decode_round_trip(code, d, max_iter=max_iter, alpha=alpha,
+                                  early_stop=early_stop, soft=True)
     torch.cuda.synchronize()
     g = {k: v.cpu().numpy() for k, v in g.items()}
     r = oracle.decode(llr, fz, max_iter=max_iter, early_stop=early_stop,
