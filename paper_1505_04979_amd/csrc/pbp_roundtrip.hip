@@ -74,6 +74,8 @@ struct RtParams {
     int32_t *iters_out;
     int64_t *pe_out;
     float *soft_out;
+    int *counter;             // [frame, exit] counters, zero between
+                              // launches; null: frames by grid stride
 };
 
 template <int M>
@@ -104,7 +106,22 @@ __global__ __launch_bounds__(RtShape<M>::NT, 8) void bp_round_trip_kernel(RtPara
 
     auto frozen_at = [&](int i) { return (P.frozen[i >> 6] >> (i & 63)) & 1; };
 
-    for (int64_t f = blockIdx.x; f < P.B; f += gridDim.x) {
+    // Frames come from the handle's device counter, so that groups whose
+    // frames stop early take more of them; the counter numbers frames in 32
+    // bits, so batches beyond 2^30 frames are split by grid stride instead.
+    __shared__ int64_t next;
+    auto take = [&](int64_t prev) -> int64_t {
+        if (!P.counter)
+            return prev < 0 ? (int64_t)blockIdx.x : prev + gridDim.x;
+        if (tid == 0)
+            next = atomicAdd(P.counter, 1);
+        __syncthreads();
+        const int64_t f = next;
+        // every thread has read it before thread 0 takes the next one
+        __syncthreads();
+        return f;
+    };
+    for (int64_t f = take(-1); f < P.B; f = take(f)) {
         // R inputs of each stage's PE (R at column j, rows a and b), as the
         // R pass last read them: the channel at column 1, 0 elsewhere
         float kRa[M + 1], kRb[M + 1];
@@ -238,6 +255,13 @@ __global__ __launch_bounds__(RtShape<M>::NT, 8) void bp_round_trip_kernel(RtPara
         }
         __syncthreads();
     }
+    // every group has taken its last frame number before it counts itself
+    // out; the last one out rewinds both counters for the next launch
+    if (P.counter && tid == 0 &&
+        atomicAdd(P.counter + 1, 1) == (int)gridDim.x - 1) {
+        atomicExch(P.counter, 0);
+        atomicExch(P.counter + 1, 0);
+    }
 }
 
 template <int M>
@@ -289,6 +313,7 @@ extern "C" int32_t pbp_decode_round_trip(const pbp_code *code, const float *llr,
     P.iters_out = iters_out;
     P.pe_out = pe_out;
     P.soft_out = soft_out;
+    P.counter = B <= (int64_t(1) << 30) ? code->d_counter : nullptr;
     hipStream_t st = (hipStream_t)stream;
     hipError_t e;
     switch (code->m) {
