@@ -150,3 +150,45 @@ def test_large_batch_sampled_parity(env):
     gs = {k: v[sel].cpu().numpy() for k, v in g.items()}
     r = oracle.decode(d[sel].cpu().numpy(), fz, soft=True, schedule=RT)
     assert_parity(gs, r, fz)
+
+
+def test_graph_capture_replays(env):
+    """pbp_decode_round_trip captured once in a graph and replayed on new
+    LLRs matches eager calls and the oracle, replay after replay: the frame
+    counter the workgroups take frames from is left at zero for the next
+    launch."""
+    pbp, torch = env
+    N, K, B = 1024, 512, 600
+    print(f"[parity] round-trip graph replay N={N} B={B}", flush=True)
+    fz = frozen_mask(N, K)
+    code = code_of(pbp, N, K)
+    _, _, llr0 = make_frames(N, K, B, 2.5, stream=(11 << 16) + 97)
+    static_llr = torch.from_numpy(llr0).cuda()
+    out = pbp.pbp_decode_round_trip(code, static_llr, soft=True)
+    torch.cuda.synchronize()
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        pbp.pbp_decode_round_trip(code, static_llr, soft=True, out=out,
+                                  stream=s)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        pbp.pbp_decode_round_trip(code, static_llr, soft=True, out=out,
+                                  stream=s)
+    torch.cuda.synchronize()
+    for rep in range(4):
+        _, _, llr = make_frames(N, K, B, 2.0 + 0.5 * rep,
+                                stream=(11 << 16) + 98 + rep)
+        static_llr.copy_(torch.from_numpy(llr))
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        got = {k: v.cpu().numpy() for k, v in out.items()}
+        eager = pbp.pbp_decode_round_trip(code, torch.from_numpy(llr).cuda(),
+                                          soft=True)
+        torch.cuda.synchronize()
+        for k in got:
+            assert np.array_equal(got[k], eager[k].cpu().numpy()), (rep, k)
+        idx = np.arange(0, B, 50)
+        r = oracle.decode(llr[idx], fz, soft=True, schedule=RT)
+        assert_parity({k: v[idx] for k, v in got.items()}, r, fz)
