@@ -136,8 +136,8 @@ int32_t pbp_decode(const pbp_code *code, const float *llr, int64_t B,
  * every R output for stages 1, ..., m (from the R just computed at column j
  * and this pass's L at column j+1).  Arguments, layouts, ownership and the
  * stop test as for pbp_decode; pe_out counts both passes, m N PE
- * activations per iteration.  opts->freezing must be 0 and N <= 1024.
- * Errors: as pbp_decode; PBP_EUNSUPPORTED for freezing or N > 1024. */
+ * activations per iteration.  opts->freezing must be 0 and N <= 2048.
+ * Errors: as pbp_decode; PBP_EUNSUPPORTED for freezing or N > 2048. */
 int32_t pbp_decode_round_trip(const pbp_code *code, const float *llr,
                               int64_t B, const pbp_decode_opts *opts,
                               uint8_t *info_out, int32_t *iters_out,

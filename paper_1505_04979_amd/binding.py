@@ -207,7 +207,7 @@ def pbp_decode(code, llr, opts=None, pe=True, soft=False, out=None,
     ``opts`` is a pbp_decode_opts or None (then keyword options apply).
     Pass ``out`` (a dict of preallocated tensors) to avoid allocation.
     ``schedule``: "single" (pbp_decode) or "round_trip"
-    (pbp_decode_round_trip: no freezing, N <= 1024).
+    (pbp_decode_round_trip: no freezing, N <= 2048).
     """
     import torch
     if opts is None:
@@ -242,7 +242,7 @@ def pbp_decode_round_trip(code, llr, opts=None, pe=True, soft=False, out=None,
                           stream=None, **kw):
     """pbp_decode with the round-trip schedule (the C entry point
     pbp_decode_round_trip): same arguments and outputs; no freezing,
-    N <= 1024."""
+    N <= 2048."""
     return pbp_decode(code, llr, opts=opts, pe=pe, soft=soft, out=out,
                       stream=stream, schedule="round_trip", **kw)
 

@@ -1,4 +1,4 @@
-// Round-trip BP schedule for codes up to N = 1024.
+// Round-trip BP schedule for codes up to N = 2048.
 //
 // The other common reading of Section II-A's schedule: each iteration first
 // computes every L output of eq. (1), stage m down to stage 1 (from the L
@@ -14,7 +14,7 @@
 // the R pass, and the R pass keeps the two R inputs it read at stage j for
 // the next L pass: 4 m values per thread in registers.  LDS holds only a
 // ping-pong pair of columns per direction, the decisions and the encoder's
-// bits (about 20 KB at N = 1024).
+// bits (about 19 KB at N = 1024, 37 KB at N = 2048).
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -24,6 +24,9 @@
 namespace {
 
 constexpr float kInf = __builtin_inff();
+
+// longest code: one thread per PE of a stage (N / 2 <= 1024 threads)
+constexpr int kMaxRoundTripLog = 11;
 
 // alpha g(x, y) of eq. (1): y with the sign of x folded in, clamped to
 // [-|x|, |x|] (a selection, exact), then scaled once
@@ -269,7 +272,7 @@ hipError_t launch_rt(const pbp_code *c, const RtParams &P, hipStream_t st)
 {
     using S = RtShape<M>;
     // at most 64 VGPRs: eight wavefronts per SIMD, 32 per compute unit
-    const int per_cu = S::NW >= 8 ? 4 : 32 / S::NW;
+    const int per_cu = 32 / S::NW;
     int64_t grid = (int64_t)(c->cus > 0 ? c->cus : 256) * per_cu;
     if (grid > P.B)
         grid = P.B;
@@ -294,7 +297,7 @@ extern "C" int32_t pbp_decode_round_trip(const pbp_code *code, const float *llr,
         opts->freeze_walk < 0 || opts->freeze_walk > 2 ||
         !(opts->alpha > 0.0f) || !(opts->alpha < kInf))
         return PBP_EINVAL;
-    if (opts->freezing || code->m > pbp::kMaxLdsLog)
+    if (opts->freezing || code->m > kMaxRoundTripLog)
         return PBP_EUNSUPPORTED;
     if (B == 0)
         return PBP_OK;
@@ -327,6 +330,7 @@ extern "C" int32_t pbp_decode_round_trip(const pbp_code *code, const float *llr,
     case 8: e = launch_rt<8>(code, P, st); break;
     case 9: e = launch_rt<9>(code, P, st); break;
     case 10: e = launch_rt<10>(code, P, st); break;
+    case 11: e = launch_rt<11>(code, P, st); break;
     default: return PBP_EUNSUPPORTED;
     }
     return e == hipSuccess ? PBP_OK : PBP_EDEVICE;

@@ -71,6 +71,7 @@ CASES = [
     (512, 256, 2.5, 80),
     (1024, 512, 3.0, 160),
     (1024, 512, 1.5, 64),
+    (2048, 1024, 2.5, 40),
 ]
 
 
@@ -120,8 +121,8 @@ def test_rejects_what_it_does_not_run(env):
     d = torch.zeros((4, 1024), dtype=torch.float32, device="cuda")
     with pytest.raises(pbp.PbpError):
         pbp.pbp_decode(code, d, freezing=True, schedule="round_trip")
-    long = code_of(pbp, 2048, 1024)
-    d2 = torch.zeros((2, 2048), dtype=torch.float32, device="cuda")
+    long = code_of(pbp, 4096, 2048)
+    d2 = torch.zeros((2, 4096), dtype=torch.float32, device="cuda")
     with pytest.raises(pbp.PbpError):
         pbp.pbp_decode(long, d2, schedule="round_trip")
     # an empty batch is a no-op
