@@ -108,6 +108,9 @@ __global__ __launch_bounds__(RtShape<M>::NT, 8) void bp_round_trip_kernel(RtPara
     const float alpha = P.alpha;
 
     auto frozen_at = [&](int i) { return (P.frozen[i >> 6] >> (i & 63)) & 1; };
+    // the frozen bits of this thread's rows at stage m (offset 1: rows 2 t
+    // and 2 t + 1), read once for the launch
+    const int fz_m = act ? (int)(frozen_at(2 * tid) | (frozen_at(2 * tid + 1) << 1)) : 0;
 
     // Frames come from the handle's device counter, so that groups whose
     // frames stop early take more of them; the counter numbers frames in 32
@@ -156,8 +159,8 @@ __global__ __launch_bounds__(RtShape<M>::NT, 8) void bp_round_trip_kernel(RtPara
                     const int a = row_a(j), b = a + h;
                     float La, Lb;
                     if (j == M) {
-                        La = frozen_at(a) ? kInf : 0.0f;
-                        Lb = frozen_at(b) ? kInf : 0.0f;
+                        La = (fz_m & 1) ? kInf : 0.0f;
+                        Lb = (fz_m & 2) ? kInf : 0.0f;
                     } else {
                         La = sm.L[(j + 1) & 1][a];
                         Lb = sm.L[(j + 1) & 1][b];
@@ -201,8 +204,8 @@ __global__ __launch_bounds__(RtShape<M>::NT, 8) void bp_round_trip_kernel(RtPara
                     sm.R[(j + 1) & 1][b] = rb;
                     if (j == M) {
                         // h = 1: rows a, a + 1; decisions at column m+1
-                        sm.u[a] = frozen_at(a) ? 0 : (uint8_t)(ra < 0.0f);
-                        sm.u[b] = frozen_at(b) ? 0 : (uint8_t)(rb < 0.0f);
+                        sm.u[a] = (fz_m & 1) ? 0 : (uint8_t)(ra < 0.0f);
+                        sm.u[b] = (fz_m & 2) ? 0 : (uint8_t)(rb < 0.0f);
                     }
                 }
                 if (j < M)
