@@ -15,6 +15,8 @@ Functions and the passages they follow:
                      freezing; G-matrix stop; Section IV PE count.
   unrolled_forward   eq. (1) with per-(iteration, stage, direction) scales.
   unrolled_grad      reverse-mode derivative of unrolled_forward.
+  unrolled_grad_mag  the magnitude sums of unrolled_grad's terms (sizes the
+                     rounding error of a gradient computed in FP32).
 """
 
 import ctypes
@@ -64,6 +66,8 @@ def _lib(prec):
                                                 P, ctypes.c_int, P, P]
         lib.oracle_unrolled_grad.argtypes = [ctypes.c_int, P, ctypes.c_int64,
                                              P, ctypes.c_int, P, P, P, P]
+        lib.oracle_unrolled_grad_mag.argtypes = \
+            lib.oracle_unrolled_grad.argtypes
         expect = 4 if prec == "f32" else 8
         assert lib.oracle_real_bytes() == expect
         _libs[prec] = lib
@@ -177,4 +181,28 @@ def unrolled_grad(llr, frozen, alpha, dout, prec="f64"):
     dl = np.empty((B, N), np.float64)
     _lib(prec).oracle_unrolled_grad(m, _ptr(frozen), B, _ptr(llr), T,
                                     _ptr(alpha), _ptr(dout), _ptr(da), _ptr(dl))
+    return da, dl
+
+
+def unrolled_grad_mag(llr, frozen, alpha, dout, prec="f64"):
+    """(A_alpha (T, m, 2), A_llr (B, N)): for every element of unrolled_grad's
+    result, the sum of the magnitudes of the path terms it adds up (|dout|,
+    scales, |g0| for the scale gradients; no sign factors).  An FP32
+    accumulation of those terms in any order is within n u A of the exact
+    sum, n the roundings along the longest path and u = 2^-24."""
+    llr = np.ascontiguousarray(llr, dtype=np.float32)
+    B, N = llr.shape
+    m = _m_of(N)
+    alpha = np.ascontiguousarray(alpha, dtype=np.float64)
+    if not (alpha > 0).all():
+        raise ValueError("scales must be positive")
+    T = alpha.shape[0]
+    frozen = np.ascontiguousarray(frozen, dtype=np.uint8)
+    dout = np.ascontiguousarray(dout, dtype=np.float64)
+    assert dout.shape == (B, N)
+    da = np.empty((T, m, 2), np.float64)
+    dl = np.empty((B, N), np.float64)
+    _lib(prec).oracle_unrolled_grad_mag(m, _ptr(frozen), B, _ptr(llr), T,
+                                        _ptr(alpha), _ptr(dout), _ptr(da),
+                                        _ptr(dl))
     return da, dl

@@ -386,24 +386,35 @@ int oracle_unrolled_forward(int m, const uint8_t *frozen, int64_t B,
 }
 
 /* Route the adjoint d of g0(x, y) to x or y (see above); an infinite
- * operand takes nothing. */
-static void g0_back(real x, real y, double d, double *dx, double *dy)
+ * operand takes nothing.  With mag set, the sign factor is dropped (see
+ * unrolled_grad_core). */
+static void g0_back(real x, real y, double d, double *dx, double *dy, int mag)
 {
     if (fabs(x) <= fabs(y)) {
         if (isfinite(x))
-            *dx += d * (double)sgn(y);
+            *dx += mag ? d : d * (double)sgn(y);
     } else {
         if (isfinite(y))
-            *dy += d * (double)sgn(x);
+            *dy += mag ? d : d * (double)sgn(x);
     }
 }
 
 /* Gradients of sum_i dout[f][i] * out[f][i] with respect to the scales
  * (dalpha, T x m x 2, accumulated over frames) and to the channel LLRs
- * (dllr, B x n, nullable).  Both are written (not accumulated). */
-int oracle_unrolled_grad(int m, const uint8_t *frozen, int64_t B,
-                         const float *llr, int T, const double *alpha,
-                         const double *dout, double *dalpha, double *dllr)
+ * (dllr, B x n, nullable).  Both are written (not accumulated).
+ *
+ * Every gradient element is a sum, over the paths of the graph, of products
+ * of a dout value, scales, signs and (for dalpha) one forward g0 value.
+ * With mag set, the same accumulation runs on the magnitudes of those
+ * factors (|dout|, no sign factors, |g0|): the result is the sum of the
+ * magnitudes of the terms, the quantity that the rounding error of any
+ * order of accumulating them is proportional to (a running-error bound for
+ * sums of products).  It is not a gradient; it sizes the comparison of
+ * gradients computed in another precision. */
+static int unrolled_grad_core(int m, const uint8_t *frozen, int64_t B,
+                              const float *llr, int T, const double *alpha,
+                              const double *dout, double *dalpha,
+                              double *dllr, int mag)
 {
     if (m < 1 || m > 16 || B < 0 || T < 1)
         return -1;
@@ -430,7 +441,8 @@ int oracle_unrolled_grad(int m, const uint8_t *frozen, int64_t B,
             memset(dLprev, 0, sizeof(double) * col);
             if (t == T)
                 for (int i = 0; i < n; i++)
-                    dR[AT(m + 1, i)] = dout[fr * n + i];
+                    dR[AT(m + 1, i)] = mag ? fabs(dout[fr * n + i])
+                                           : dout[fr * n + i];
             for (int j = m; j >= 1; j--) {
                 const int h = n >> j;
                 const size_t ai = ((size_t)(t - 1) * m + (j - 1)) * 2;
@@ -453,21 +465,24 @@ int oracle_unrolled_grad(int m, const uint8_t *frozen, int64_t B,
                     double oLb = fLb ? dL[AT(j, b)] : 0.0;
                     double oRa = fRa ? dR[AT(j + 1, a)] : 0.0;
                     double oRb = fRb ? dR[AT(j + 1, b)] : 0.0;
+                    const double vA = mag ? fabs((double)gA) : (double)gA;
+                    const double v1 = mag ? fabs((double)g1) : (double)g1;
+                    const double vB = mag ? fabs((double)gB) : (double)gB;
                     if (fLa)
-                        dalpha[ai + 0] += oLa * (double)gA;
+                        dalpha[ai + 0] += oLa * vA;
                     if (fLb)
-                        dalpha[ai + 0] += oLb * (double)g1;
+                        dalpha[ai + 0] += oLb * v1;
                     if (fRa)
-                        dalpha[ai + 1] += oRa * (double)gB;
+                        dalpha[ai + 1] += oRa * vB;
                     if (fRb)
-                        dalpha[ai + 1] += oRb * (double)g1;
+                        dalpha[ai + 1] += oRb * v1;
                     double dgA = (double)aL * oLa;
                     double dg1 = (double)aL * oLb + (double)aR * oRb;
                     double dgB = (double)aR * oRa;
                     double dLa = 0, dLb = oLb, dRa = 0, dRb = oRb, ds = 0;
-                    g0_back(La, s, dgA, &dLa, &ds);
-                    g0_back(La, Ra, dg1, &dLa, &dRa);
-                    g0_back(Ra, s, dgB, &dRa, &ds);
+                    g0_back(La, s, dgA, &dLa, &ds, mag);
+                    g0_back(La, Ra, dg1, &dLa, &dRa, mag);
+                    g0_back(Ra, s, dgB, &dRa, &ds, mag);
                     if (isfinite(s)) {
                         dLb += ds;
                         dRb += ds;
@@ -488,4 +503,22 @@ int oracle_unrolled_grad(int m, const uint8_t *frozen, int64_t B,
     }
     free(Ls); free(Rs); free(dL); free(dLprev); free(dR);
     return 0;
+}
+
+int oracle_unrolled_grad(int m, const uint8_t *frozen, int64_t B,
+                         const float *llr, int T, const double *alpha,
+                         const double *dout, double *dalpha, double *dllr)
+{
+    return unrolled_grad_core(m, frozen, B, llr, T, alpha, dout, dalpha, dllr,
+                              0);
+}
+
+/* The magnitude sums of oracle_unrolled_grad's terms (mag mode above);
+ * scales must be positive. */
+int oracle_unrolled_grad_mag(int m, const uint8_t *frozen, int64_t B,
+                             const float *llr, int T, const double *alpha,
+                             const double *dout, double *dalpha, double *dllr)
+{
+    return unrolled_grad_core(m, frozen, B, llr, T, alpha, dout, dalpha, dllr,
+                              1);
 }

@@ -112,3 +112,45 @@ def test_llr_gradient_matches_central_differences():
             checked += 1
             assert abs(dl[f, i] - fd1) <= 1e-5 * max(1.0, abs(fd1)), (f, i)
     assert checked >= 0.8 * B * N
+
+
+def test_magnitude_sums_n2_closed_form_and_bound():
+    """unrolled_grad_mag: at N = 2 the only terms are dout * y0 (scale),
+    dout (y1) and dout * aR (y0), so the sums are their magnitudes; at any
+    size every sum is at least the gradient's magnitude (triangle
+    inequality), with the same zero pattern, and equals it when every
+    term has one sign (dout >= 0 on a noiseless all-zero word, where every
+    message is positive)."""
+    rng = np.random.default_rng(4)
+    y = rng.standard_normal((40, 2)).astype(np.float32) * 2
+    fz = np.array([1, 0], np.uint8)
+    T = 3
+    alpha = rng.uniform(0.5, 1.2, size=(T, 1, 2))
+    dout = np.zeros((40, 2))
+    dout[:, 1] = rng.standard_normal(40)
+    Aa, Al = oracle.unrolled_grad_mag(y, fz, alpha, dout, prec="f64")
+    aR = alpha[T - 1, 0, 1]
+    want = np.zeros_like(Aa)
+    want[T - 1, 0, 1] = np.sum(np.abs(dout[:, 1] * y[:, 0]))
+    assert np.allclose(Aa, want, rtol=1e-13, atol=0)
+    assert np.allclose(Al[:, 1], np.abs(dout[:, 1]), rtol=1e-15)
+    assert np.allclose(Al[:, 0], np.abs(dout[:, 1]) * aR, rtol=1e-15)
+
+    N, K, T, B = 64, 32, 5, 6
+    m = 6
+    fz = frozen_mask(N, K)
+    _, _, llr = make_frames(N, K, B, 1.5, stream=92)
+    alpha = rng.uniform(0.7, 1.1, size=(T, m, 2))
+    dout = rng.standard_normal((B, N)) * (fz == 0)
+    da, dl = oracle.unrolled_grad(llr, fz, alpha, dout)
+    Aa, Al = oracle.unrolled_grad_mag(llr, fz, alpha, dout)
+    for g, A in ((da, Aa), (dl, Al)):
+        assert (A >= np.abs(g) * (1 - 1e-12)).all()
+        assert np.array_equal(A == 0, g == 0)
+    # one sign throughout: the all-zero codeword without noise
+    pos = np.full((2, N), 3.0, np.float32)
+    dpos = np.abs(rng.standard_normal((2, N))) * (fz == 0)
+    da, dl = oracle.unrolled_grad(pos, fz, alpha, dpos)
+    Aa, Al = oracle.unrolled_grad_mag(pos, fz, alpha, dpos)
+    assert np.allclose(Aa, da, rtol=1e-12, atol=0)
+    assert np.allclose(Al, dl, rtol=1e-12, atol=0)
