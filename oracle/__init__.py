@@ -17,6 +17,8 @@ Functions and the passages they follow:
   unrolled_grad      reverse-mode derivative of unrolled_forward.
   unrolled_grad_mag  the magnitude sums of unrolled_grad's terms (sizes the
                      rounding error of a gradient computed in FP32).
+  sc_decode          successive cancellation, the decoder whose scheduling
+                     tree Section III maps onto the factor graph (min-sum f).
 """
 
 import ctypes
@@ -68,6 +70,9 @@ def _lib(prec):
                                              P, ctypes.c_int, P, P, P, P]
         lib.oracle_unrolled_grad_mag.argtypes = \
             lib.oracle_unrolled_grad.argtypes
+        lib.oracle_sc_decode.argtypes = [ctypes.c_int, P, ctypes.c_int64, P,
+                                         P, P]
+        lib.oracle_sc_decode.restype = ctypes.c_int
         expect = 4 if prec == "f32" else 8
         assert lib.oracle_real_bytes() == expect
         _libs[prec] = lib
@@ -206,3 +211,20 @@ def unrolled_grad_mag(llr, frozen, alpha, dout, prec="f64"):
                                         _ptr(alpha), _ptr(dout), _ptr(da),
                                         _ptr(dl))
     return da, dl
+
+
+def sc_decode(llr, frozen, prec="f32", leaf=False):
+    """Successive-cancellation decisions (B, N) uint8 of FP32 LLRs (B, N);
+    with ``leaf`` also the LLR reaching each leaf, (B, N)."""
+    llr = np.ascontiguousarray(llr, dtype=np.float32)
+    if llr.ndim == 1:
+        llr = llr[None, :]
+    B, N = llr.shape
+    m = _m_of(N)
+    frozen = np.ascontiguousarray(frozen, dtype=np.uint8)
+    uhat = np.empty((B, N), np.uint8)
+    lf = np.empty((B, N), _real(prec)) if leaf else None
+    rc = _lib(prec).oracle_sc_decode(m, _ptr(frozen), B, _ptr(llr), _ptr(uhat),
+                                     _ptr(lf))
+    assert rc == 0
+    return (uhat, lf) if leaf else uhat

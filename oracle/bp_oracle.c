@@ -522,3 +522,66 @@ int oracle_unrolled_grad_mag(int m, const uint8_t *frozen, int64_t B,
     return unrolled_grad_core(m, frozen, B, llr, T, alpha, dout, dalpha, dllr,
                               1);
 }
+
+/* ------------------------------------------------------------------------
+ * Successive-cancellation (SC) decoding: the decoder whose scheduling tree
+ * Section III maps onto the factor graph (each CSFG of the BP graph is a
+ * node of the SC tree, and Lemma 1's ML decision of a frozen CSFG is the
+ * decision SC's subtree would reach no better than).  For G = F^{(x)m} in
+ * natural order, G_n = F (x) G_{n/2}, so x = [(u_a ^ u_b) G_{n/2} |
+ * u_b G_{n/2}] for the halves u_a, u_b of u.  A node of size n with the LLRs
+ * L of its n codeword bits therefore decodes
+ *   u_a from f(L[i], L[i + n/2])                     (the code u_a G_{n/2}),
+ *   u_b from g(L[i], L[i + n/2], c_a[i]) = L[i + n/2] + (1 - 2 c_a[i]) L[i]
+ *       with c_a = u_a G_{n/2}, the left subtree's re-encoded decisions,
+ * and returns its own re-encoding [c_a ^ c_b | c_b].  f is the min-sum
+ * check-node rule sign(a) sign(b) min(|a|, |b|) (exact: a selection, no
+ * scaling); g rounds once.  A leaf takes u = 0 at a frozen position and
+ * [LLR < 0] at an information position, in increasing index order.
+ * ---------------------------------------------------------------------- */
+static real sc_f(real a, real b) { return sgn(a) * sgn(b) * fmin(fabs(a), fabs(b)); }
+
+static real sc_g(real a, real b, uint8_t c) { return b + (c ? -a : a); }
+
+/* work: 2n reals; leaf: n reals (the LLR at each leaf) or NULL */
+static void sc_node(int n, const real *L, const uint8_t *frozen, uint8_t *u,
+                    uint8_t *x, real *work, real *leaf)
+{
+    if (n == 1) {
+        if (leaf)
+            leaf[0] = L[0];
+        u[0] = frozen[0] ? 0 : (L[0] < 0);
+        x[0] = u[0];
+        return;
+    }
+    const int h = n / 2;
+    real *Lc = work;            /* the child's n/2 LLRs */
+    for (int i = 0; i < h; i++)
+        Lc[i] = sc_f(L[i], L[i + h]);
+    sc_node(h, Lc, frozen, u, x, work + h, leaf);
+    for (int i = 0; i < h; i++)
+        Lc[i] = sc_g(L[i], L[i + h], x[i]);
+    sc_node(h, Lc, frozen + h, u + h, x + h, work + h, leaf ? leaf + h : NULL);
+    for (int i = 0; i < h; i++)
+        x[i] ^= x[i + h];
+}
+
+/* uhat: B x n source-word decisions; leaf: B x n leaf LLRs, or NULL.
+ * Returns 0, or -1 on bad arguments. */
+int oracle_sc_decode(int m, const uint8_t *frozen, int64_t B, const float *llr,
+                     uint8_t *uhat, real *leaf)
+{
+    if (m < 0 || m > 20 || B < 0)
+        return -1;
+    const int n = 1 << m;
+    real *L = malloc(sizeof(real) * (size_t)n);
+    real *work = malloc(sizeof(real) * 2 * (size_t)n);
+    uint8_t *x = malloc((size_t)n);
+    for (int64_t f = 0; f < B; f++) {
+        for (int i = 0; i < n; i++)
+            L[i] = (real)llr[f * n + i];
+        sc_node(n, L, frozen, uhat + f * n, x, work, leaf ? leaf + f * n : NULL);
+    }
+    free(L); free(work); free(x);
+    return 0;
+}
