@@ -27,16 +27,20 @@ namespace {
 
 constexpr float kInf = __builtin_inff();
 
-// The min-sum term of eq. (1): alpha * sign(x) * sign(y) * min(|x|, |y|).
-// A zero result may carry either sign; no value or decision depends on it.
-__device__ __forceinline__ float gmin(float x, float y, float alpha)
+// The min-sum term of eq. (1), alpha * sign(x) * sign(y) * min(|x|, |y|),
+// is gmin(ax, x, y) with ax = salpha(x): y clamped to [-|x|, |x|] (one
+// median of three: exact, a selection) times alpha carrying the sign of x
+// (one product, rounded once and symmetrically in sign).  The two terms of a
+// PE with the same first operand share ax.  A zero result may carry either
+// sign; no value or decision depends on it.
+__device__ __forceinline__ float salpha(float x, float alpha)
 {
-    // sign(x) sign(y) min(|x|, |y|) is y, its sign flipped when x < 0,
-    // clamped to [-|x|, |x|]: one median of three (exact, a selection); the
-    // product with alpha then rounds once, symmetrically in sign
-    const float t = __uint_as_float(__float_as_uint(y) ^
-                                    (__float_as_uint(x) & 0x80000000u));
-    return alpha * __builtin_amdgcn_fmed3f(-fabsf(x), t, fabsf(x));
+    return __builtin_copysignf(alpha, x);
+}
+
+__device__ __forceinline__ float gmin(float ax, float x, float y)
+{
+    return ax * __builtin_amdgcn_fmed3f(-fabsf(x), y, fabsf(x));
 }
 
 // x F^{(x)6} over the 64 bits of a word (bit i = position i): at each level
@@ -95,10 +99,11 @@ __device__ __forceinline__ void pe_eq1(float La, float Lb, float Ra, float Rb,
                                        float &oRa, float &oRb)
 {
     const float sm = Lb + Rb;
-    const float g1 = gmin(La, Ra, alpha);
-    oLa = gmin(La, sm, alpha);
+    const float aLa = salpha(La, alpha);
+    const float g1 = gmin(aLa, La, Ra);
+    oLa = gmin(aLa, La, sm);
     oLb = Lb + g1;
-    oRa = gmin(Ra, sm, alpha);
+    oRa = gmin(salpha(Ra, alpha), Ra, sm);
     oRb = Rb + g1;
 }
 
@@ -305,10 +310,11 @@ __device__ __forceinline__ void decode_frame(const DecodeParams &P,
                         if (q0 + u * NT < N / 2) {
                             const int a = ia[u], b = a + h;
                             const float sm = Lb[u] + Rb[u];
-                            const float g1 = gmin(La[u], Ra[u], alpha);
-                            Lj[a] = gmin(La[u], sm, alpha);
+                            const float aLa = salpha(La[u], alpha);
+                            const float g1 = gmin(aLa, La[u], Ra[u]);
+                            Lj[a] = gmin(aLa, La[u], sm);
                             Lj[b] = Lb[u] + g1;
-                            Rw[a] = gmin(Ra[u], sm, alpha);
+                            Rw[a] = gmin(salpha(Ra[u], alpha), Ra[u], sm);
                             Rw[b] = Rb[u] + g1;
                         }
                     }

@@ -40,14 +40,20 @@ namespace {
 
 constexpr float kInf = __builtin_inff();
 
-__device__ __forceinline__ float gmin(float x, float y, float alpha)
+// sign(y) min(|x|, |y|): y clamped to [-|x|, |x|] (a selection, exact)
+__device__ __forceinline__ float clampm(float x, float y)
 {
-    // sign(x) sign(y) min(|x|, |y|) is y, its sign flipped when x < 0,
-    // clamped to [-|x|, |x|]: one median of three (exact, a selection); the
-    // product with alpha then rounds once, symmetrically in sign
-    const float t = __uint_as_float(__float_as_uint(y) ^
-                                    (__float_as_uint(x) & 0x80000000u));
-    return alpha * __builtin_amdgcn_fmed3f(-fabsf(x), t, fabsf(x));
+    return __builtin_amdgcn_fmed3f(-fabsf(x), y, fabsf(x));
+}
+
+// alpha carrying the sign of x.  The min-sum term of eq. (1),
+// alpha sign(x) sign(y) min(|x|, |y|), is salpha(x) * clampm(x, y): one
+// product, rounded once and symmetrically in sign.  A PE's two terms with
+// the same first operand share salpha, so a PE costs 11 FP32 operations.  A
+// zero result may carry either sign; no value or decision depends on it.
+__device__ __forceinline__ float salpha(float x, float alpha)
+{
+    return __builtin_copysignf(alpha, x);
 }
 
 __device__ __forceinline__ void wave_sync()
@@ -334,10 +340,11 @@ struct Decoder {
         const float Ra = (J == 1) ? ch[QA] : R[QA];
         const float Rb = (J == 1) ? ch[QB] : R[QB];
         const float s = Lb + Rb;
-        const float g1 = gmin(La, Ra, alpha);
-        const float la = gmin(La, s, alpha);
+        const float aLa = salpha(La, alpha);
+        const float g1 = aLa * clampm(La, Ra);
+        const float la = aLa * clampm(La, s);
         const float lbv = Lb + g1;
-        R[QA] = gmin(Ra, s, alpha);
+        R[QA] = salpha(Ra, alpha) * clampm(Ra, s);
         R[QB] = Rb + g1;
         if constexpr (J == 1) {
             if constexpr (ES) {
