@@ -143,6 +143,21 @@ int32_t pbp_decode_round_trip(const pbp_code *code, const float *llr,
                               uint8_t *info_out, int32_t *iters_out,
                               int64_t *pe_out, float *soft_out, void *stream);
 
+/* Successive-cancellation decoding (the decoder whose scheduling tree
+ * Section III maps onto the factor graph; its ML comparison with a frozen
+ * CSFG is the argument of Lemma 1's use).  Source bits are decided in
+ * increasing position order: a node over n positions with LLRs L decodes its
+ * first half from f(L[i], L[i + n/2]) = sign * sign * min (exact, unscaled
+ * min-sum), then its second half from L[i + n/2] + (1 - 2c) L[i] (one
+ * rounding), c the first half's re-encoded bits; a leaf takes 0 at a frozen
+ * position and [LLR < 0] otherwise.
+ *   llr       device, B x N FP32 channel LLRs
+ *   info_out  device, B x K uint8, the decided information bits
+ *   leaf_out  device, B x N FP32, or NULL: the LLR reaching each leaf
+ * B >= 0.  Errors: PBP_EINVAL, PBP_EDEVICE. */
+int32_t pbp_decode_sc(const pbp_code *code, const float *llr, int64_t B,
+                      uint8_t *info_out, float *leaf_out, void *stream);
+
 /* ---- Mixed-code persistent decoding ----------------------------------
  * One batch may mix codes of different lengths and rates (each frame names
  * its code); the whole batch is decoded by one launch of persistent

@@ -54,6 +54,8 @@ _SIGNATURES = [
     ("pbp_decode_round_trip", ctypes.c_int32,
      [_P, _P, ctypes.c_int64, ctypes.POINTER(pbp_decode_opts), _P, _P, _P, _P,
       _P]),
+    ("pbp_decode_sc", ctypes.c_int32,
+     [_P, _P, ctypes.c_int64, _P, _P, _P]),
     ("pbp_mixed_plan_create", ctypes.c_int32,
      [_P, ctypes.c_int32, ctypes.c_int64, ctypes.POINTER(_P)]),
     ("pbp_mixed_plan_destroy", None, [_P]),
@@ -223,9 +225,10 @@ def pbp_decode(code, llr, opts=None, pe=True, soft=False, out=None,
         o["pe"] = torch.empty((B,), dtype=torch.int64, device=dev)
     if soft and "soft" not in o:
         o["soft"] = torch.empty((B, code.N), dtype=torch.float32, device=dev)
-    if schedule not in ("single", "round_trip"):
+    names = {"single": "pbp_decode", "round_trip": "pbp_decode_round_trip"}
+    if schedule not in names:
         raise ValueError(f"unknown schedule {schedule!r}")
-    name = "pbp_decode" if schedule == "single" else "pbp_decode_round_trip"
+    name = names[schedule]
     _check(name, getattr(lib(), name)(
         code.handle, _dev_ptr(llr, torch.float32, (B, code.N), "llr"), B,
         ctypes.byref(opts),
@@ -245,6 +248,28 @@ def pbp_decode_round_trip(code, llr, opts=None, pe=True, soft=False, out=None,
     N <= 2048."""
     return pbp_decode(code, llr, opts=opts, pe=pe, soft=soft, out=out,
                       stream=stream, schedule="round_trip", **kw)
+
+
+def pbp_decode_sc(code, llr, leaf=False, out=None, stream=None):
+    """Successive-cancellation decoding of FP32 LLRs (B, N) on the device.
+
+    Returns a dict of device tensors: ``info`` (B, K) uint8 and, when asked,
+    ``leaf`` (B, N) float32, the LLR reaching each leaf."""
+    import torch
+    B = int(llr.shape[0])
+    dev = llr.device
+    o = dict(out or {})
+    if "info" not in o:
+        o["info"] = torch.empty((B, code.K), dtype=torch.uint8, device=dev)
+    if leaf and "leaf" not in o:
+        o["leaf"] = torch.empty((B, code.N), dtype=torch.float32, device=dev)
+    _check("pbp_decode_sc", lib().pbp_decode_sc(
+        code.handle, _dev_ptr(llr, torch.float32, (B, code.N), "llr"), B,
+        _dev_ptr(o["info"], torch.uint8, (B, code.K), "info"),
+        _dev_ptr(o.get("leaf") if leaf else None, torch.float32, (B, code.N),
+                 "leaf"),
+        _stream(stream)))
+    return o
 
 
 def pbp_unrolled_forward(code, llr, alpha, ckpt=True, out=None, stream=None):

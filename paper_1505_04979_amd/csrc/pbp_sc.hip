@@ -1,0 +1,185 @@
+// Successive-cancellation (SC) decoding on the GPU: the decoder whose
+// scheduling tree Section III maps onto the BP factor graph.  It decodes the
+// same codes as pbp_decode (natural order, G = F^{(x)m}) and serves as the
+// error-rate reference of Section III's comparison of a frozen CSFG's ML
+// decision with SC.
+//
+// One wavefront per frame, persistent over a grid stride.  The node at
+// depth d of the SC tree covers 2^(m-d) consecutive source bits; its LLRs
+// live in LDS (alpha: depth d at offset N - 2^(m-d+1), 2^(m-d) values; the
+// channel LLRs of depth 0 are read in place).  The re-encoded bits of every
+// completed subtree are kept in place in one byte per source position
+// (beta): the subtree over positions [s, s + n) holds x = u G_n there, so
+// completing a right subtree turns its parent's bits into
+// [x_left ^ x_right | x_right] by n XORs.  Leaf i follows leaf i - 1 by one
+// g step at the depth where the path turns right (the depth of the lowest
+// set bit of i) and f steps down to the leaf.
+#include <hip/hip_runtime.h>
+
+#include "pbp_internal.h"
+
+namespace {
+
+// f: the min-sum check-node rule sign(a) sign(b) min(|a|, |b|), exact (a
+// selection: b clamped to [-|a|, |a|] with the sign of a applied)
+__device__ __forceinline__ float sc_f(float a, float b)
+{
+    const float t = __uint_as_float(__float_as_uint(b) ^
+                                    (__float_as_uint(a) & 0x80000000u));
+    return __builtin_amdgcn_fmed3f(-fabsf(a), t, fabsf(a));
+}
+
+// g: b + (1 - 2c) a, one rounding (the sign flip is exact)
+__device__ __forceinline__ float sc_g(float a, float b, uint8_t c)
+{
+    return b + (c ? -a : a);
+}
+
+__device__ __forceinline__ void wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+struct SCParams {
+    const float *llr;
+    int64_t B;
+    const uint64_t *frozen_words;   // bit i of word i >> 6: position i frozen
+    const int32_t *info_pos;
+    int32_t K;
+    uint8_t *info_out;
+    float *leaf_out;                // B x N or null: the LLR at each leaf
+};
+
+template <int M>
+__global__ __launch_bounds__(64) void sc_decode_kernel(SCParams P)
+{
+    constexpr int N = 1 << M;
+    extern __shared__ __align__(16) unsigned char smem[];
+    float *alpha = reinterpret_cast<float *>(smem);          // N - 1 floats
+    uint8_t *beta = smem + sizeof(float) * N;                // N bytes
+    const int lane = (int)threadIdx.x;
+
+    for (int64_t frame = blockIdx.x; frame < P.B; frame += gridDim.x) {
+        const float *ch = P.llr + frame * N;
+        // depth d >= 1 starts at N - 2^(m-d+1); depth 0 is the channel
+        auto col = [&](int d) -> float * { return alpha + (N - (N >> (d - 1))); };
+        for (int i = 0; i < N; i++) {
+            // the depth whose node turns right at leaf i (0 for leaf 0: the
+            // path starts at the root with f steps)
+            int p = 0;
+            if (i > 0) {
+                const int t = __builtin_ctz(i);
+                p = M - 1 - t;
+                const int n = 1 << t;                // child size
+                const float *src = p == 0 ? ch : col(p);
+                float *dst = col(p + 1);
+                const uint8_t *c = beta + (i - n);
+                for (int j = lane; j < n; j += 64)
+                    dst[j] = sc_g(src[j], src[j + n], c[j]);
+                wave_sync();
+                p++;
+            }
+            for (int d = p; d < M; d++) {
+                const int n = N >> (d + 1);
+                const float *src = d == 0 ? ch : col(d);
+                float *dst = col(d + 1);
+                for (int j = lane; j < n; j += 64)
+                    dst[j] = sc_f(src[j], src[j + n]);
+                wave_sync();
+            }
+            // leaf decision: 0 at a frozen position, else [LLR < 0]
+            const float v = M == 0 ? ch[0] : col(M)[0];
+            const bool fz = (P.frozen_words[i >> 6] >> (i & 63)) & 1;
+            if (lane == 0) {
+                beta[i] = fz ? 0 : (v < 0.0f ? 1 : 0);
+                if (P.leaf_out)
+                    P.leaf_out[frame * N + i] = v;
+            }
+            wave_sync();
+            // completed right subtrees: parent bits [x_l ^ x_r | x_r]
+            for (int t = 0; t < M && ((i >> t) & 1); t++) {
+                const int n = 1 << t;
+                const int s = i + 1 - 2 * n;
+                for (int j = lane; j < n; j += 64)
+                    beta[s + j] ^= beta[s + n + j];
+                wave_sync();
+            }
+        }
+        // beta now holds x = u G, the re-encoded word; the decided source
+        // bits are its transform (G is its own inverse)
+        for (int h = 1; h < N; h <<= 1) {
+            for (int q = lane; q < N / 2; q += 64) {
+                const int a = ((q / h) * 2 * h) + (q % h);
+                beta[a] ^= beta[a + h];
+            }
+            wave_sync();
+        }
+        uint8_t *out = P.info_out + frame * P.K;
+        for (int k = lane; k < P.K; k += 64)
+            out[k] = beta[P.info_pos[k]];
+        wave_sync();
+    }
+}
+
+template <int M>
+hipError_t launch_sc(const pbp_code *c, SCParams &P, hipStream_t st)
+{
+    constexpr int N = 1 << M;
+    const size_t lds = sizeof(float) * N + N;
+    int64_t grid = P.B;
+    const int64_t cap = (int64_t)c->cus * 32;
+    if (grid > cap)
+        grid = cap;
+    auto kern = sc_decode_kernel<M>;
+    hipError_t e = hipFuncSetAttribute((const void *)kern,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)lds);
+    if (e != hipSuccess)
+        return e;
+    hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(64), lds, st, P);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+extern "C" int32_t pbp_decode_sc(const pbp_code *code, const float *llr,
+                                 int64_t B, uint8_t *info_out, float *leaf_out,
+                                 void *stream)
+{
+    if (!code || B < 0)
+        return PBP_EINVAL;
+    if (B == 0)
+        return PBP_OK;
+    if (!llr || (!info_out && code->K > 0))
+        return PBP_EINVAL;
+    SCParams P{};
+    P.llr = llr;
+    P.B = B;
+    P.frozen_words = code->d_frozen_words;
+    P.info_pos = code->d_info_pos;
+    P.K = code->K;
+    P.info_out = info_out;
+    P.leaf_out = leaf_out;
+    hipStream_t st = (hipStream_t)stream;
+    hipError_t e;
+    switch (code->m) {
+    case 1: e = launch_sc<1>(code, P, st); break;
+    case 2: e = launch_sc<2>(code, P, st); break;
+    case 3: e = launch_sc<3>(code, P, st); break;
+    case 4: e = launch_sc<4>(code, P, st); break;
+    case 5: e = launch_sc<5>(code, P, st); break;
+    case 6: e = launch_sc<6>(code, P, st); break;
+    case 7: e = launch_sc<7>(code, P, st); break;
+    case 8: e = launch_sc<8>(code, P, st); break;
+    case 9: e = launch_sc<9>(code, P, st); break;
+    case 10: e = launch_sc<10>(code, P, st); break;
+    case 11: e = launch_sc<11>(code, P, st); break;
+    case 12: e = launch_sc<12>(code, P, st); break;
+    case 13: e = launch_sc<13>(code, P, st); break;
+    case 14: e = launch_sc<14>(code, P, st); break;
+    default: return PBP_EUNSUPPORTED;
+    }
+    return e == hipSuccess ? PBP_OK : PBP_EDEVICE;
+}
