@@ -129,6 +129,24 @@ int32_t pbp_decode(const pbp_code *code, const float *llr, int64_t B,
                    int32_t *iters_out, int64_t *pe_out, float *soft_out,
                    void *stream);
 
+/* pbp_decode for callers that cannot allocate device memory (code under
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same decoding, arguments and results bit for bit, with the scratch of
+ * the persistent kernels (the N = 1024 kernel's frame counter, the message
+ * state of codes longer than 1024) taken from a static 64 MiB device array
+ * instead of the handle, and no allocation of any kind.  Each GPU holds one
+ * such array until the process ends; codes longer than 1024 run at most as
+ * many resident workgroups as state slots fit in it (683 at N = 2048, 315 at
+ * N = 4096, 68 at N = 16384).  Every call on a GPU shares that array, so
+ * calls that overlap on one GPU (two streams, or two threads) race; order
+ * them on one stream.  B must be at most 2^30.
+ * Errors: as pbp_decode; PBP_EINVAL also for B > 2^30, PBP_EDEVICE when the
+ * array's address cannot be obtained. */
+int32_t pbp_decode_noalloc(const pbp_code *code, const float *llr, int64_t B,
+                           const pbp_decode_opts *opts, uint8_t *info_out,
+                           int32_t *iters_out, int64_t *pe_out,
+                           float *soft_out, void *stream);
+
 /* The round-trip schedule, the other common reading of Section II-A's
  * schedule (pbp_decode runs the single left-to-right sweep): each iteration
  * computes every L output of eq. (1) for stages m, m-1, ..., 1 (from the L

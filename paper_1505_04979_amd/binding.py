@@ -51,6 +51,9 @@ _SIGNATURES = [
     ("pbp_decode", ctypes.c_int32,
      [_P, _P, ctypes.c_int64, ctypes.POINTER(pbp_decode_opts), _P, _P, _P, _P,
       _P]),
+    ("pbp_decode_noalloc", ctypes.c_int32,
+     [_P, _P, ctypes.c_int64, ctypes.POINTER(pbp_decode_opts), _P, _P, _P, _P,
+      _P]),
     ("pbp_decode_round_trip", ctypes.c_int32,
      [_P, _P, ctypes.c_int64, ctypes.POINTER(pbp_decode_opts), _P, _P, _P, _P,
       _P]),
@@ -208,8 +211,9 @@ def pbp_decode(code, llr, opts=None, pe=True, soft=False, out=None,
     int32, ``pe`` (B,) int64 when asked, ``soft`` (B, N) float32 when asked.
     ``opts`` is a pbp_decode_opts or None (then keyword options apply).
     Pass ``out`` (a dict of preallocated tensors) to avoid allocation.
-    ``schedule``: "single" (pbp_decode) or "round_trip"
-    (pbp_decode_round_trip: no freezing, N <= 2048).
+    ``schedule``: "single" (pbp_decode), "round_trip"
+    (pbp_decode_round_trip: no freezing, N <= 2048) or "noalloc"
+    (pbp_decode_noalloc: the single sweep with static scratch).
     """
     import torch
     if opts is None:
@@ -225,7 +229,8 @@ def pbp_decode(code, llr, opts=None, pe=True, soft=False, out=None,
         o["pe"] = torch.empty((B,), dtype=torch.int64, device=dev)
     if soft and "soft" not in o:
         o["soft"] = torch.empty((B, code.N), dtype=torch.float32, device=dev)
-    names = {"single": "pbp_decode", "round_trip": "pbp_decode_round_trip"}
+    names = {"single": "pbp_decode", "round_trip": "pbp_decode_round_trip",
+             "noalloc": "pbp_decode_noalloc"}
     if schedule not in names:
         raise ValueError(f"unknown schedule {schedule!r}")
     name = names[schedule]
@@ -248,6 +253,15 @@ def pbp_decode_round_trip(code, llr, opts=None, pe=True, soft=False, out=None,
     N <= 2048."""
     return pbp_decode(code, llr, opts=opts, pe=pe, soft=soft, out=out,
                       stream=stream, schedule="round_trip", **kw)
+
+
+def pbp_decode_noalloc(code, llr, opts=None, pe=True, soft=False, out=None,
+                       stream=None, **kw):
+    """pbp_decode through the C entry point pbp_decode_noalloc (its scratch
+    is a static device array; the library allocates nothing): same
+    arguments and outputs.  Pass ``out`` to allocate nothing here either."""
+    return pbp_decode(code, llr, opts=opts, pe=pe, soft=soft, out=out,
+                      stream=stream, schedule="noalloc", **kw)
 
 
 def pbp_decode_sc(code, llr, leaf=False, out=None, stream=None):

@@ -6,6 +6,8 @@
 // (larger N).  N = 1024 goes to the register-resident decoder instead.
 #include <hip/hip_runtime.h>
 
+#include <mutex>
+
 #include "pbp_generic_decoder.h"
 #include "pbp_internal.h"
 #include "pbp_r10.h"
@@ -61,8 +63,11 @@ size_t decode_lds_bytes(bool gstate)
     return lds_bytes<M>(gstate ? 1 : 0);
 }
 
+// state, slots: the message state of codes longer than 1024 (one slot of
+// (m + 1) N floats per resident workgroup, so at most `slots` groups)
 template <int M>
-hipError_t launch_decode(const pbp_code *c, DecodeParams &P, hipStream_t st)
+hipError_t launch_decode(const pbp_code *c, DecodeParams &P, float *state,
+                         int64_t slots, hipStream_t st)
 {
     constexpr int N = 1 << M;
     constexpr bool G = M > pbp::kMaxLdsLog;
@@ -70,10 +75,10 @@ hipError_t launch_decode(const pbp_code *c, DecodeParams &P, hipStream_t st)
     const size_t lds = decode_lds_bytes<M>(G);
     int64_t grid = P.B;
     if (G) {
-        P.state = c->d_state;
+        P.state = state;
         P.state_stride = c->state_floats_per_slot;
-        if (grid > c->state_slots)
-            grid = c->state_slots;
+        if (grid > slots)
+            grid = slots;
     }
     if (grid > (1ll << 30))
         grid = 1ll << 30;
@@ -105,10 +110,20 @@ extern "C" int32_t pbp_encode(const pbp_code *code, const uint8_t *info,
     return hipGetLastError() == hipSuccess ? PBP_OK : PBP_EDEVICE;
 }
 
-extern "C" int32_t pbp_decode(const pbp_code *code, const float *llr, int64_t B,
-                              const pbp_decode_opts *opts, uint8_t *info_out,
-                              int32_t *iters_out, int64_t *pe_out,
-                              float *soft_out, void *stream)
+namespace {
+
+// Device scratch of one decode call: the [frame, exit] counter pair of the
+// N = 1024 kernel and the message-state slots of codes longer than 1024.
+struct Scratch {
+    int *counter;
+    float *state;
+    int64_t slots;
+};
+
+int32_t decode_impl(const pbp_code *code, const float *llr, int64_t B,
+                    const pbp_decode_opts *opts, uint8_t *info_out,
+                    int32_t *iters_out, int64_t *pe_out, float *soft_out,
+                    void *stream, const Scratch *sc)
 {
     if (!code || !opts || B < 0)
         return PBP_EINVAL;
@@ -147,25 +162,125 @@ extern "C" int32_t pbp_decode(const pbp_code *code, const float *llr, int64_t B,
     if (code->m == pbp::r10::M && code->d_fzw10 && aligned16 &&
         B <= (int64_t(1) << 30)) {
         e = pbp::r10::launch(code, llr, B, opts, info_out, iters_out, pe_out,
-                             soft_out, st);
+                             soft_out, sc->counter, st);
         return e == hipSuccess ? PBP_OK : PBP_EDEVICE;
     }
     switch (code->m) {
-    case 1: e = launch_decode<1>(code, P, st); break;
-    case 2: e = launch_decode<2>(code, P, st); break;
-    case 3: e = launch_decode<3>(code, P, st); break;
-    case 4: e = launch_decode<4>(code, P, st); break;
-    case 5: e = launch_decode<5>(code, P, st); break;
-    case 6: e = launch_decode<6>(code, P, st); break;
-    case 7: e = launch_decode<7>(code, P, st); break;
-    case 8: e = launch_decode<8>(code, P, st); break;
-    case 9: e = launch_decode<9>(code, P, st); break;
-    case 10: e = launch_decode<10>(code, P, st); break;
-    case 11: e = launch_decode<11>(code, P, st); break;
-    case 12: e = launch_decode<12>(code, P, st); break;
-    case 13: e = launch_decode<13>(code, P, st); break;
-    case 14: e = launch_decode<14>(code, P, st); break;
+    case 1: e = launch_decode<1>(code, P, sc->state, sc->slots, st); break;
+    case 2: e = launch_decode<2>(code, P, sc->state, sc->slots, st); break;
+    case 3: e = launch_decode<3>(code, P, sc->state, sc->slots, st); break;
+    case 4: e = launch_decode<4>(code, P, sc->state, sc->slots, st); break;
+    case 5: e = launch_decode<5>(code, P, sc->state, sc->slots, st); break;
+    case 6: e = launch_decode<6>(code, P, sc->state, sc->slots, st); break;
+    case 7: e = launch_decode<7>(code, P, sc->state, sc->slots, st); break;
+    case 8: e = launch_decode<8>(code, P, sc->state, sc->slots, st); break;
+    case 9: e = launch_decode<9>(code, P, sc->state, sc->slots, st); break;
+    case 10: e = launch_decode<10>(code, P, sc->state, sc->slots, st); break;
+    case 11: e = launch_decode<11>(code, P, sc->state, sc->slots, st); break;
+    case 12: e = launch_decode<12>(code, P, sc->state, sc->slots, st); break;
+    case 13: e = launch_decode<13>(code, P, sc->state, sc->slots, st); break;
+    case 14: e = launch_decode<14>(code, P, sc->state, sc->slots, st); break;
     default: return PBP_EUNSUPPORTED;
     }
     return e == hipSuccess ? PBP_OK : PBP_EDEVICE;
+}
+
+}  // namespace
+
+extern "C" int32_t pbp_decode(const pbp_code *code, const float *llr, int64_t B,
+                              const pbp_decode_opts *opts, uint8_t *info_out,
+                              int32_t *iters_out, int64_t *pe_out,
+                              float *soft_out, void *stream)
+{
+    if (!code)
+        return PBP_EINVAL;
+    const Scratch sc{code->d_counter, code->d_state, code->state_slots};
+    return decode_impl(code, llr, B, opts, info_out, iters_out, pe_out,
+                       soft_out, stream, &sc);
+}
+
+// ---- Decoding without allocation (pbp_decode_noalloc) --------------------
+//
+// The scratch of these calls is one static device array per GPU, so a call
+// needs no allocation: its first 256 bytes hold the counter pair, the rest
+// the message-state slots of codes longer than 1024.
+namespace {
+
+constexpr size_t kScratchBytes = size_t(64) << 20;
+constexpr size_t kScratchHead = 256;
+constexpr int kMaxDevices = 64;
+
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+// The device address of this GPU's scratch, looked up once per device with
+// that device current.  (In host code the array's name is only a stand-in:
+// every kernel argument, fill and copy uses this address.)
+std::mutex g_scratch_mu;
+void *g_scratch_addr[kMaxDevices];
+
+int32_t scratch_address(void **out)
+{
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices)
+        return PBP_EDEVICE;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_addr[dev]) {
+        void *ptr = nullptr;
+        if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr)
+            return PBP_EDEVICE;
+        g_scratch_addr[dev] = ptr;
+    }
+    *out = g_scratch_addr[dev];
+    return PBP_OK;
+}
+
+// the counter pair starts each call at zero (a kernel, not a memset, so that
+// a caller may capture the call in a graph)
+__global__ void clear_counters_kernel(int *counter)
+{
+    if (threadIdx.x < 2)
+        counter[threadIdx.x] = 0;
+}
+
+// message-state slots that fit the scratch (codes longer than 1024)
+int64_t scratch_slots(const pbp_code *code)
+{
+    if (code->m <= pbp::kMaxLdsLog)
+        return INT64_MAX;
+    const int64_t slot = (int64_t)sizeof(float) * code->state_floats_per_slot;
+    return (int64_t)((kScratchBytes - kScratchHead) / slot);
+}
+
+}  // namespace
+
+extern "C" int32_t pbp_decode_noalloc(const pbp_code *code, const float *llr,
+                                      int64_t B, const pbp_decode_opts *opts,
+                                      uint8_t *info_out, int32_t *iters_out,
+                                      int64_t *pe_out, float *soft_out,
+                                      void *stream)
+{
+    if (!code || !opts || B < 0)
+        return PBP_EINVAL;
+    // the N = 1024 kernel numbers frames with a 32-bit counter
+    if (B > (int64_t(1) << 30))
+        return PBP_EINVAL;
+    void *base = nullptr;
+    const int32_t st = scratch_address(&base);
+    if (st != PBP_OK)
+        return st;
+    Scratch sc{};
+    sc.counter = reinterpret_cast<int *>(base);
+    sc.state = reinterpret_cast<float *>(static_cast<unsigned char *>(base) +
+                                         kScratchHead);
+    sc.slots = scratch_slots(code);
+    if (code->m > pbp::kMaxLdsLog && sc.slots < 1)
+        return PBP_EUNSUPPORTED;
+    if (B > 0 && code->m == pbp::r10::M) {
+        hipLaunchKernelGGL(clear_counters_kernel, dim3(1), dim3(64), 0,
+                           (hipStream_t)stream, sc.counter);
+        if (hipGetLastError() != hipSuccess)
+            return PBP_EDEVICE;
+    }
+    return decode_impl(code, llr, B, opts, info_out, iters_out, pe_out,
+                       soft_out, stream, &sc);
 }

@@ -63,7 +63,7 @@ size_t smem_bytes();
 hipError_t launch(const pbp_code *c, const float *llr, int64_t B,
                   const pbp_decode_opts *o, uint8_t *info_out,
                   int32_t *iters_out, int64_t *pe_out, float *soft_out,
-                  hipStream_t st);
+                  int *counter, hipStream_t st);
 
 }  // namespace r10
 }  // namespace pbp

@@ -40,12 +40,12 @@ size_t smem_bytes() { return sizeof(Smem); }
 hipError_t launch(const pbp_code *c, const float *llr, int64_t B,
                   const pbp_decode_opts *o, uint8_t *info_out,
                   int32_t *iters_out, int64_t *pe_out, float *soft_out,
-                  hipStream_t st)
+                  int *counter, hipStream_t st)
 {
     Params P{};
     P.llr = llr;
     P.B = B;
-    P.counter = c->d_counter;
+    P.counter = counter;
     P.fzw = c->d_fzw10;
     P.info_pos = c->d_info_pos;
     P.K = c->K;
