@@ -19,6 +19,9 @@ Functions and the passages they follow:
                      rounding error of a gradient computed in FP32).
   sc_decode          successive cancellation, the decoder whose scheduling
                      tree Section III maps onto the factor graph (min-sum f).
+  decode_quant       decode with saturating b-bit fixed-point messages (the
+                     hardware cost framing of Sections I and V).
+  quantize           the channel quantizer of decode_quant.
 """
 
 import ctypes
@@ -44,6 +47,10 @@ class Opts(ctypes.Structure):
                 ("freezing", ctypes.c_int32), ("freeze_input", ctypes.c_int32),
                 ("freeze_walk", ctypes.c_int32), ("alpha", ctypes.c_double),
                 ("schedule", ctypes.c_int32)]
+
+
+class QFmt(ctypes.Structure):
+    _fields_ = [("bits", ctypes.c_int32), ("frac", ctypes.c_int32)]
 
 
 _libs = {}
@@ -73,6 +80,13 @@ def _lib(prec):
         lib.oracle_sc_decode.argtypes = [ctypes.c_int, P, ctypes.c_int64, P,
                                          P, P]
         lib.oracle_sc_decode.restype = ctypes.c_int
+        lib.oracle_decode_q.argtypes = [ctypes.c_int, P, ctypes.c_int64, P,
+                                        ctypes.POINTER(Opts),
+                                        ctypes.POINTER(QFmt), P, P, P, P]
+        lib.oracle_decode_q.restype = ctypes.c_int
+        lib.oracle_quantize.argtypes = [ctypes.c_float, ctypes.c_int32,
+                                        ctypes.c_int32]
+        lib.oracle_quantize.restype = ctypes.c_int32
         expect = 4 if prec == "f32" else 8
         assert lib.oracle_real_bytes() == expect
         _libs[prec] = lib
@@ -228,3 +242,41 @@ def sc_decode(llr, frozen, prec="f32", leaf=False):
                                      _ptr(lf))
     assert rc == 0
     return (uhat, lf) if leaf else uhat
+
+
+def quantize(llr, bits=8, frac=3):
+    """decode_quant's channel quantizer: clamp(round(LLR 2^F), -Q, Q)."""
+    f = _lib("f64").oracle_quantize
+    a = np.asarray(llr, np.float32)
+    return np.array([f(float(v), int(bits), int(frac)) for v in a.ravel()],
+                    np.int32).reshape(a.shape)
+
+
+def decode_quant(llr, frozen, bits=8, frac=3, max_iter=40, early_stop=True,
+                 freezing=False, freeze_input=INPUT_TOTAL,
+                 freeze_walk=WALK_ONE_PER_ITER, alpha=0.9375, soft=False):
+    """decode() with saturating fixed-point messages (single sweep).  Returns
+    the same dict; ``soft`` holds sat(R + L) at column m+1 as int32."""
+    llr = np.ascontiguousarray(llr, dtype=np.float32)
+    if llr.ndim == 1:
+        llr = llr[None, :]
+    B, N = llr.shape
+    m = _m_of(N)
+    frozen = np.ascontiguousarray(frozen, dtype=np.uint8)
+    o = Opts(int(max_iter), int(bool(early_stop)), int(bool(freezing)),
+             int(freeze_input), int(freeze_walk), float(alpha), 0)
+    qf = QFmt(int(bits), int(frac))
+    uhat = np.empty((B, N), np.uint8)
+    iters = np.empty(B, np.int32)
+    pe = np.empty(B, np.int64)
+    sf = np.empty((B, N), np.int32) if soft else None
+    rc = _lib("f64").oracle_decode_q(m, _ptr(frozen), B, _ptr(llr),
+                                     ctypes.byref(o), ctypes.byref(qf),
+                                     _ptr(uhat), _ptr(iters), _ptr(pe),
+                                     _ptr(sf))
+    if rc != 0:
+        raise ValueError("oracle_decode_q rejected its arguments")
+    out = {"uhat": uhat, "info": uhat[:, frozen == 0], "iters": iters, "pe": pe}
+    if soft:
+        out["soft"] = sf
+    return out

@@ -585,3 +585,159 @@ int oracle_sc_decode(int m, const uint8_t *frozen, int64_t B, const float *llr,
     free(L); free(work); free(x);
     return 0;
 }
+
+/* ------------------------------------------------------------------------
+ * Fixed-point messages: the decoder of decode_frame (single sweep, early
+ * stop, freezing) with every message a saturating b-bit integer, the form
+ * in which the paper counts a PE's cost in hardware (Sections I and V).
+ * The paper fixes no format; the reading:
+ *   Q = 2^(b-1) - 1; every message lies in [-Q, Q];
+ *   channel: q = clamp(round(LLR 2^F), -Q, Q), F fraction bits, rounding
+ *            half away from zero;
+ *   gq(x, y) = sign(x) sign(y) ((a min(|x|, |y|) + 8) >> 4),
+ *            a = round(16 alpha) (15 for alpha = 0.9375): the scaled minimum
+ *            rounded to the nearest integer, halves up (truncation would
+ *            turn every magnitude-1 message into 0);
+ *   sat(v) = clamp(v, -Q, Q) for every sum of eq. (1);
+ *   +-inf of the frozen prior and of a frozen CSFG's L become +-Q;
+ *   hard decisions (eq. (2), the stop test, the output) take the exact sum's
+ *   sign: v < 0.
+ * ---------------------------------------------------------------------- */
+typedef struct {
+    int32_t bits;          /* message width b, 2..16 */
+    int32_t frac;          /* fraction bits F of the channel quantizer */
+} oracle_qfmt;
+
+static int32_t q_sat(int32_t v, int32_t Q) { return v > Q ? Q : (v < -Q ? -Q : v); }
+
+static int32_t q_sgn(int32_t v) { return (v > 0) - (v < 0); }
+
+static int32_t q_g(int32_t a16, int32_t x, int32_t y)
+{
+    const int32_t ax = x < 0 ? -x : x, ay = y < 0 ? -y : y;
+    const int32_t mn = ax < ay ? ax : ay;
+    return q_sgn(x) * q_sgn(y) * ((a16 * mn + 8) >> 4);
+}
+
+/* one quantized channel value */
+int32_t oracle_quantize(float llr, int32_t bits, int32_t frac)
+{
+    const int32_t Q = (1 << (bits - 1)) - 1;
+    const double v = round((double)llr * ldexp(1.0, frac));
+    return v > Q ? Q : (v < -Q ? -Q : (int32_t)v);
+}
+
+static int decode_frame_q(int m, const uint8_t *frozen, const float *llr,
+                          const oracle_opts *o, const oracle_qfmt *qf,
+                          uint8_t *uhat, int64_t *pe_out, int32_t *soft)
+{
+    const int n = 1 << m;
+    const int32_t Q = (1 << (qf->bits - 1)) - 1;
+    const int32_t a16 = (int32_t)lround(o->alpha * 16.0);
+    int32_t *L = calloc((size_t)(m + 2) * n, sizeof(int32_t));
+    int32_t *R = calloc((size_t)(m + 2) * n, sizeof(int32_t));
+    uint8_t *dec = calloc((size_t)n, 1);
+    uint8_t *xh = malloc((size_t)n), *uh = malloc((size_t)n);
+    uint8_t *xe = malloc((size_t)n);
+    int *p = calloc((size_t)m + 1, sizeof(int));
+    int64_t pe = 0;
+    int t;
+
+    for (int i = 0; i < n; i++) {
+        R[AT(1, i)] = oracle_quantize(llr[i], qf->bits, qf->frac);
+        L[AT(m + 1, i)] = frozen[i] ? Q : 0;
+    }
+    for (t = 1; t <= o->max_iter; t++) {
+        int walking = 1;
+        for (int j = 1; j <= m; j++) {
+            const int h = n >> j;
+            const int f = p[j - 1] * 2 * h;
+            for (int a = f; a < n; a++) {
+                if (a & h)
+                    continue;
+                const int b = a + h;
+                const int32_t La = L[AT(j + 1, a)], Lb = L[AT(j + 1, b)];
+                const int32_t Ra = R[AT(j, a)], Rb = R[AT(j, b)];
+                const int32_t s = q_sat(Lb + Rb, Q);
+                L[AT(j, b)] = q_sat(Lb + q_g(a16, La, Ra), Q);
+                L[AT(j, a)] = q_g(a16, La, s);
+                R[AT(j + 1, a)] = q_g(a16, Ra, s);
+                R[AT(j + 1, b)] = q_sat(Rb + q_g(a16, La, Ra), Q);
+                pe++;
+            }
+            if (!o->freezing)
+                continue;
+            if (p[j] < 2 * p[j - 1])
+                p[j] = 2 * p[j - 1];
+            while (p[j] < (1 << j)) {
+                if (o->freeze_walk == WALK_ONE_PER_ITER && !walking)
+                    break;
+                const int k = p[j], r0 = k * h;
+                for (int r = 0; r < h; r++) {
+                    const int32_t v = o->freeze_input
+                                          ? R[AT(j + 1, r0 + r)] + L[AT(j + 1, r0 + r)]
+                                          : R[AT(j + 1, r0 + r)];
+                    xh[r] = v < 0;
+                }
+                oracle_encode(m - j, xh, uh);
+                int pass = 1;
+                for (int r = 0; r < h && pass; r++)
+                    pass = !(uh[r] && frozen[r0 + r]);
+                if (!pass)
+                    break;
+                for (int r = 0; r < h; r++) {
+                    L[AT(j + 1, r0 + r)] = xh[r] ? -Q : Q;
+                    dec[r0 + r] = uh[r];
+                }
+                p[j] = k + 1;
+                if (o->freeze_walk == WALK_ONE_PER_ITER) {
+                    walking = 0;
+                    break;
+                }
+                if (o->freeze_walk == WALK_ONE_PER_STAGE)
+                    break;
+            }
+        }
+        const int fm = o->freezing ? p[m] : 0;
+        for (int i = 0; i < n; i++)
+            uhat[i] = i < fm ? dec[i] : (frozen[i] ? 0 : R[AT(m + 1, i)] < 0);
+        if (o->freezing && fm == n)
+            break;
+        if (o->early_stop) {
+            oracle_encode(m, uhat, xe);
+            int same = 1;
+            for (int i = 0; i < n && same; i++)
+                same = xe[i] == (R[AT(1, i)] + L[AT(1, i)] < 0);
+            if (same)
+                break;
+        }
+    }
+    if (t > o->max_iter)
+        t = o->max_iter;
+    if (soft) {
+        const int fm = o->freezing ? p[m] : 0;
+        for (int i = 0; i < n; i++)
+            soft[i] = i < fm ? (dec[i] ? -Q : Q)
+                             : q_sat(R[AT(m + 1, i)] + L[AT(m + 1, i)], Q);
+    }
+    *pe_out = pe;
+    free(L); free(R); free(dec); free(xh); free(uh); free(xe); free(p);
+    return t;
+}
+
+/* As oracle_decode (single sweep only) with fixed-point messages; soft
+ * (nullable) receives sat(R + L) at column m+1 as integers. */
+int oracle_decode_q(int m, const uint8_t *frozen, int64_t B, const float *llr,
+                    const oracle_opts *o, const oracle_qfmt *qf, uint8_t *uhat,
+                    int32_t *iters, int64_t *pe, int32_t *soft)
+{
+    if (m < 1 || m > 20 || B < 0 || !o || !qf || o->max_iter < 1 ||
+        o->schedule != 0 || qf->bits < 2 || qf->bits > 16 || qf->frac < 0 ||
+        qf->frac > 16)
+        return -1;
+    const int64_t n = (int64_t)1 << m;
+    for (int64_t f = 0; f < B; f++)
+        iters[f] = decode_frame_q(m, frozen, llr + f * n, o, qf, uhat + f * n,
+                                  pe + f, soft ? soft + f * n : NULL);
+    return 0;
+}
