@@ -161,6 +161,25 @@ int32_t pbp_decode_round_trip(const pbp_code *code, const float *llr,
                               uint8_t *info_out, int32_t *iters_out,
                               int64_t *pe_out, float *soft_out, void *stream);
 
+/* pbp_decode with saturating b-bit fixed-point messages, the integer
+ * arithmetic of a hardware decoder in which the paper counts a PE's cost
+ * (Sections I and V; the paper fixes no format).  Every message lies in
+ * [-Q, Q], Q = 2^(bits-1) - 1: the channel is clamp(round(LLR 2^frac))
+ * (halves away from zero); eq. (1)'s scaled minimum is
+ * sign sign ((a min(|x|, |y|) + 8) >> 4), a = round(16 alpha); its sums
+ * saturate; +-Q replaces the +-inf of the frozen prior and of frozen CSFGs;
+ * hard decisions take the exact sum's sign.  Same schedule, stop test,
+ * freezing walk, iteration and PE counts as pbp_decode.
+ *   bits      2..8 (messages are stored as bytes); frac 0..16
+ *   soft_out  device, B x N int8, or NULL: sat(R + L) at column m+1 (+-Q
+ *             inside frozen CSFGs)
+ * Other arguments as pbp_decode.  N <= 4096.
+ * Errors: as pbp_decode; PBP_EUNSUPPORTED for N > 4096. */
+int32_t pbp_decode_quant(const pbp_code *code, const float *llr, int64_t B,
+                         const pbp_decode_opts *opts, int32_t bits,
+                         int32_t frac, uint8_t *info_out, int32_t *iters_out,
+                         int64_t *pe_out, int8_t *soft_out, void *stream);
+
 /* Successive-cancellation decoding (the decoder whose scheduling tree
  * Section III maps onto the factor graph; its ML comparison with a frozen
  * CSFG is the argument of Lemma 1's use).  Source bits are decided in

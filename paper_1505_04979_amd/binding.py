@@ -57,6 +57,9 @@ _SIGNATURES = [
     ("pbp_decode_round_trip", ctypes.c_int32,
      [_P, _P, ctypes.c_int64, ctypes.POINTER(pbp_decode_opts), _P, _P, _P, _P,
       _P]),
+    ("pbp_decode_quant", ctypes.c_int32,
+     [_P, _P, ctypes.c_int64, ctypes.POINTER(pbp_decode_opts), ctypes.c_int32,
+      ctypes.c_int32, _P, _P, _P, _P, _P]),
     ("pbp_decode_sc", ctypes.c_int32,
      [_P, _P, ctypes.c_int64, _P, _P, _P]),
     ("pbp_mixed_plan_create", ctypes.c_int32,
@@ -262,6 +265,37 @@ def pbp_decode_noalloc(code, llr, opts=None, pe=True, soft=False, out=None,
     arguments and outputs.  Pass ``out`` to allocate nothing here either."""
     return pbp_decode(code, llr, opts=opts, pe=pe, soft=soft, out=out,
                       stream=stream, schedule="noalloc", **kw)
+
+
+def pbp_decode_quant(code, llr, bits=8, frac=3, opts=None, pe=True, soft=False,
+                     out=None, stream=None, **kw):
+    """pbp_decode with saturating ``bits``-bit fixed-point messages (channel
+    quantized with ``frac`` fraction bits).  Returns ``info``, ``iters``,
+    ``pe`` and, when asked, ``soft`` (B, N) int8."""
+    import torch
+    if opts is None:
+        opts = make_opts(**kw)
+    B = int(llr.shape[0])
+    dev = llr.device
+    o = dict(out or {})
+    if "info" not in o:
+        o["info"] = torch.empty((B, code.K), dtype=torch.uint8, device=dev)
+    if "iters" not in o:
+        o["iters"] = torch.empty((B,), dtype=torch.int32, device=dev)
+    if pe and "pe" not in o:
+        o["pe"] = torch.empty((B,), dtype=torch.int64, device=dev)
+    if soft and "soft" not in o:
+        o["soft"] = torch.empty((B, code.N), dtype=torch.int8, device=dev)
+    _check("pbp_decode_quant", lib().pbp_decode_quant(
+        code.handle, _dev_ptr(llr, torch.float32, (B, code.N), "llr"), B,
+        ctypes.byref(opts), int(bits), int(frac),
+        _dev_ptr(o["info"], torch.uint8, (B, code.K), "info"),
+        _dev_ptr(o["iters"], torch.int32, (B,), "iters"),
+        _dev_ptr(o.get("pe") if pe else None, torch.int64, (B,), "pe"),
+        _dev_ptr(o.get("soft") if soft else None, torch.int8, (B, code.N),
+                 "soft"),
+        _stream(stream)))
+    return o
 
 
 def pbp_decode_sc(code, llr, leaf=False, out=None, stream=None):

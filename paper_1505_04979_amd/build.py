@@ -23,7 +23,8 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libpbp.so")
 SOURCES = ["pbp_host.cpp", "pbp_decode.hip", "pbp_r10.hip", "pbp_unrolled.hip",
-           "pbp_roundtrip.hip", "pbp_mixed.hip", "pbp_sc.hip"]
+           "pbp_roundtrip.hip", "pbp_mixed.hip", "pbp_sc.hip",
+           "pbp_quant.hip"]
 
 HIPCC = os.environ.get("HIPCC", shutil.which("hipcc") or "/opt/rocm/bin/hipcc")
 ARCH = os.environ.get("PBP_OFFLOAD_ARCH", "gfx950")

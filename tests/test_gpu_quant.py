@@ -1,0 +1,98 @@
+"""GPU parity of the fixed-point decoder (pbp_decode_quant) with the
+oracle's, through the C-ABI: decided bits, iteration counts, PE counts and
+the saturated posteriors all equal (integer arithmetic, so exact), in every
+mode and three message formats, for N = 2 to 4096 including degenerate
+rates and noiseless frames; the long-code limit is rejected."""
+
+import numpy as np
+import pytest
+
+import oracle
+from helpers import frozen_mask, make_frames, noiseless_llr
+
+pytestmark = pytest.mark.gpu
+
+MODES = {
+    "plain": dict(max_iter=20, early_stop=False, freezing=False),
+    "es": dict(max_iter=40, early_stop=True, freezing=False),
+    "es_frz": dict(max_iter=40, early_stop=True, freezing=True),
+    "frz": dict(max_iter=30, early_stop=False, freezing=True),
+    "es_frz_R": dict(max_iter=40, early_stop=True, freezing=True,
+                     freeze_input=0),
+    "stage": dict(max_iter=40, early_stop=True, freezing=True, freeze_walk=1),
+    "greedy": dict(max_iter=40, early_stop=True, freezing=True, freeze_walk=2),
+}
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1505_04979_amd as pbp
+    pbp.lib()
+    return pbp, torch
+
+
+def run(env, N, K, llr, bits, frac, mode):
+    pbp, torch = env
+    fz = frozen_mask(N, K)
+    code = pbp.Code(N, K, fz)
+    o = dict(freeze_input=1, freeze_walk=0)
+    o.update(MODES[mode])
+    got = pbp.pbp_decode_quant(code, torch.from_numpy(llr).cuda(), bits=bits,
+                               frac=frac, soft=True, **o)
+    torch.cuda.synchronize()
+    ref = oracle.decode_quant(llr, fz, bits=bits, frac=frac, soft=True, **o)
+    assert np.array_equal(got["info"].cpu().numpy(), ref["info"]), "bits"
+    assert np.array_equal(got["iters"].cpu().numpy(), ref["iters"]), "iters"
+    assert np.array_equal(got["pe"].cpu().numpy(), ref["pe"]), "pe"
+    assert np.array_equal(got["soft"].cpu().numpy().astype(np.int32),
+                          ref["soft"]), "soft"
+
+
+@pytest.mark.parametrize("mode", list(MODES))
+@pytest.mark.parametrize("N,K,ebn0,B", [(2, 1, 2.0, 100), (8, 4, 2.0, 100),
+                                        (64, 32, 2.5, 200), (256, 128, 2.5, 100),
+                                        (1024, 512, 3.0, 60),
+                                        (4096, 2048, 2.5, 8)])
+def test_quant_parity(env, N, K, ebn0, B, mode):
+    print(f"[quant] N={N} K={K} mode={mode}", flush=True)
+    _, _, llr = make_frames(N, K, B, ebn0, stream=1000 + N)
+    run(env, N, K, llr, 8, 3, mode)
+
+
+@pytest.mark.parametrize("bits,frac", [(6, 1), (7, 2), (8, 1)])
+def test_quant_formats(env, bits, frac):
+    N, K = 1024, 512
+    _, _, llr = make_frames(N, K, 40, 2.5, stream=1100 + bits)
+    for mode in ("plain", "es_frz"):
+        run(env, N, K, llr, bits, frac, mode)
+
+
+@pytest.mark.parametrize("N,K", [(1024, 0), (1024, 1024), (64, 1), (64, 63)])
+def test_quant_degenerate_rates(env, N, K):
+    _, _, llr = make_frames(N, K, 20, 2.0, stream=1200 + K)
+    for mode in ("es", "es_frz"):
+        run(env, N, K, llr, 8, 3, mode)
+
+
+def test_quant_noiseless(env):
+    pbp, torch = env
+    N, K = 1024, 512
+    fz = frozen_mask(N, K)
+    u, x, _ = make_frames(N, K, 10, 2.0, stream=1300)
+    llr = noiseless_llr(x)
+    for mode in MODES:
+        run(env, N, K, llr, 8, 3, mode)
+
+
+def test_quant_rejects(env):
+    pbp, torch = env
+    code = pbp.Code(8192, 4096, frozen_mask(8192, 4096))
+    with pytest.raises(pbp.PbpError):
+        pbp.pbp_decode_quant(code, torch.zeros((1, 8192), device="cuda"))
+    code = pbp.Code(64, 32, frozen_mask(64, 32))
+    with pytest.raises(pbp.PbpError):
+        pbp.pbp_decode_quant(code, torch.zeros((1, 64), device="cuda"),
+                             bits=9)
