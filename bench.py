@@ -570,7 +570,31 @@ def bench_mixed(args, pbp, torch):
                                   out=out, reps=1)
     tune_s = time.perf_counter() - t1
     steps = max(1, args.steps // 3)
-    ms = _timed(torch, lambda: pbp.pbp_decode_mixed(
+    # both schedules at 16 wavefronts per compute unit: one launch over the
+    # batch in the caller's order (order 0), and one launch per code,
+    # longest first, after the device sort (order 1)
+    schedules = {}
+    for order in (0, 1):
+        plan.config = (order, 16)
+        ms_o = _timed(torch, lambda: pbp.pbp_decode_mixed(
+            plan, d_cof, d_lo, d_io, d_llr, opts=opts, out=out), steps, 1)
+        schedules[["single_launch", "per_code"][order]] = {
+            "ms_per_step": round(ms_o, 3),
+            "fill": round(pbp.pbp_mixed_plan_fill(plan), 4)}
+    plan.config = cfg
+    # the tuned step captured in a graph and replayed (the timed value)
+    side = torch.cuda.Stream()
+    with torch.cuda.stream(side):
+        pbp.pbp_decode_mixed(plan, d_cof, d_lo, d_io, d_llr, opts=opts,
+                             out=out, stream=side)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph, stream=side):
+        pbp.pbp_decode_mixed(plan, d_cof, d_lo, d_io, d_llr, opts=opts,
+                             out=out, stream=side)
+    torch.cuda.synchronize()
+    ms = _timed(torch, graph.replay, steps, 1)
+    ms_eager = _timed(torch, lambda: pbp.pbp_decode_mixed(
         plan, d_cof, d_lo, d_io, d_llr, opts=opts, out=out), steps, 1)
     fill = pbp.pbp_mixed_plan_fill(plan)
     pe_i = out["pe"].cpu().numpy()
@@ -636,6 +660,8 @@ def bench_mixed(args, pbp, torch):
          "codes": [list(x) for x in dims]},
         frames_per_s=round(B / ms * 1e3, 1), fill_efficiency=round(fill, 4),
         tuned_config={"order": cfg[0], "waves_per_cu": cfg[1]},
+        timed="replays of the tuned step captured in a HIP graph",
+        eager_ms_per_step=round(ms_eager, 3), schedules=schedules,
         avg_iters=round(float(iters.mean()), 3),
         pe_per_frame=round(float(pe.mean()), 1), fer=errs / B,
         roofline={"bound": "hbm", "achieved": round(long_gbs, 1),

@@ -197,8 +197,8 @@ int32_t pbp_decode_sc(const pbp_code *code, const float *llr, int64_t B,
 
 /* ---- Mixed-code persistent decoding ----------------------------------
  * One batch may mix codes of different lengths and rates (each frame names
- * its code); the whole batch is decoded by one launch of persistent
- * wavefronts fed by a device work queue.  Decoding per frame is that of
+ * its code).  Persistent wavefronts drain a device work queue, each taking
+ * the next frame when it finishes one.  Decoding per frame is that of
  * pbp_decode (same results bit for bit); only the schedule differs. */
 
 /* Plan: the codes of a mixed batch, device buffers of the work queue and of
@@ -207,13 +207,19 @@ int32_t pbp_decode_sc(const pbp_code *code, const float *llr, int64_t B,
 typedef struct pbp_mixed_plan pbp_mixed_plan;
 
 /* Launch configuration.
- *  order         0: the queue takes frames in the caller's order;
- *                1: longest code first (a counting sort on the device)
- *  waves_per_cu  resident one-wavefront groups per compute unit, 1..16
- *                (each decodes one frame at a time); codes with N >= 2048
- *                are decoded by 256-thread groups, waves_per_cu / 2 of them
- *                (at least 1, at most 4) per compute unit.  No kernel is
- *                given more groups than its occupancy allows. */
+ *  order         0: one launch for the whole batch: the queue takes frames
+ *                   in the caller's order, and one kernel dispatches on
+ *                   each frame's code length (every frame on one
+ *                   wavefront; N >= 2048 with L in the wavefront's slot);
+ *                1: frames grouped by code, longest code first: a device
+ *                   counting sort (four small kernels), then one persistent
+ *                   kernel per code, specialised for its length (N >= 2048
+ *                   on 256-thread groups)
+ *  waves_per_cu  resident wavefronts per compute unit, 1..16 (each decodes
+ *                one frame at a time); under order 1, codes with
+ *                N >= 2048 run waves_per_cu / 2 256-thread groups (at least
+ *                1, at most 4) per compute unit.  No kernel is given more
+ *                groups than its occupancy allows. */
 typedef struct {
     int32_t order;
     int32_t waves_per_cu;
@@ -222,8 +228,8 @@ typedef struct {
 /* Create a plan for up to max_frames frames (1 .. 2^30) over ncodes code
  * handles (1..16, all on one device; they must outlive the plan).  Device
  * memory: the queue (4 B per frame) and, when a code has N >= 2048, one
- * message slot per resident workgroup ((m+1) 2^m floats for the longest
- * such code, 4 workgroups per compute unit).
+ * message slot per resident wavefront ((m+1) 2^m floats for the longest
+ * such code, 16 per compute unit).
  * Default configuration: {0, 16}.  Errors: PBP_EINVAL, PBP_ENOMEM,
  * PBP_EDEVICE. */
 int32_t pbp_mixed_plan_create(const pbp_code *const *codes, int32_t ncodes,
@@ -243,18 +249,18 @@ int32_t pbp_mixed_plan_set_config(pbp_mixed_plan *plan,
  *                  naming no code of the plan is not decoded: its iteration
  *                  (and PE) count is set to 0 and its bits are not written.
  *   llr_off        device, B int64: element offset of the frame's N FP32
- *                  LLRs in llr (N = 1024 frames at 16-byte aligned
- *                  addresses take the register-resident decoder)
+ *                  LLRs in llr (any offset)
  *   info_off       device, B int64: byte offset of the frame's K decided
  *                  information bits in info_out
  *   llr            device FP32 LLR buffer (finite)
  *   opts           host, as for pbp_decode
  *   iters_out      device, B int32; pe_out device, B int64, or NULL
  * Ranges given by the offsets must lie inside the caller's buffers; output
- * ranges of different frames must not overlap.  Enqueues a few small
- * kernels (order 1) and one persistent kernel; no allocation, no memset, no
- * host synchronisation, so the call can be captured in a HIP graph and
- * replayed (the queue rewinds itself at the end of every launch).
+ * ranges of different frames must not overlap.  Enqueues one persistent
+ * kernel (order 0), or the four kernels of the sort and one persistent
+ * kernel per code (order 1); no allocation, no memset, no host
+ * synchronisation, so the call can be captured in a HIP graph and replayed
+ * (the queue rewinds itself at the end of every launch).
  * Errors: PBP_EINVAL, PBP_EDEVICE. */
 int32_t pbp_decode_mixed(pbp_mixed_plan *plan, const int32_t *code_of_frame,
                          const int64_t *llr_off, const int64_t *info_off,
@@ -276,9 +282,12 @@ int32_t pbp_mixed_plan_tune(pbp_mixed_plan *plan, const int32_t *code_of_frame,
                             int32_t *iters_out, int64_t *pe_out, int32_t reps,
                             void *stream, pbp_mixed_config *best);
 
-/* Fill efficiency of the plan's last launch: the wavefronts' time spent
- * decoding over (wavefronts x the launch's span), from device timestamps.
- * Synchronises `stream` first.  Errors: PBP_EINVAL, PBP_EDEVICE. */
+/* Fill efficiency of the plan's last pbp_decode_mixed call: the resident
+ * wavefronts' time spent decoding over (the largest launch's resident
+ * wavefronts x the call's whole span, from the first wavefront's start to
+ * the last one's end), from device timestamps; kernel tails and the gaps
+ * between the per-code launches of order 1 count as idle.  Synchronises
+ * `stream` first.  Errors: PBP_EINVAL, PBP_EDEVICE. */
 int32_t pbp_mixed_plan_fill(pbp_mixed_plan *plan, void *stream, double *fill);
 
 /* Unrolled BP with trainable scales (the decoder of eq. (1) unrolled over T

@@ -155,12 +155,9 @@ int32_t decode_impl(const pbp_code *code, const float *llr, int64_t B,
     P.soft_out = soft_out;
     hipStream_t st = (hipStream_t)stream;
     hipError_t e;
-    // the register-resident N = 1024 kernel moves LLRs and posteriors as
-    // 16-byte vectors, and numbers frames with a 32-bit device counter
-    const bool aligned16 = !(reinterpret_cast<uintptr_t>(llr) & 15) &&
-                           !(reinterpret_cast<uintptr_t>(soft_out) & 15);
-    if (code->m == pbp::r10::M && code->d_fzw10 && aligned16 &&
-        B <= (int64_t(1) << 30)) {
+    // the register-resident N = 1024 kernel numbers frames with a 32-bit
+    // device counter
+    if (code->m == pbp::r10::M && code->d_fzw10 && B <= (int64_t(1) << 30)) {
         e = pbp::r10::launch(code, llr, B, opts, info_out, iters_out, pe_out,
                              soft_out, sc->counter, st);
         return e == hipSuccess ? PBP_OK : PBP_EDEVICE;

@@ -1,22 +1,27 @@
 // Persistent decoding of a batch that mixes codes (lengths and rates).
 //
-// The work queue is built on the device: a counting sort groups the frames
-// by code (an order array of frame indices, one contiguous segment per
-// code).  Each code's segment is then drained by its own persistent kernel,
-// specialised for that code length: a pool of wavefronts, each taking the
-// next queue entry from a device counter, reading the frame's buffer
-// offsets and decoding the whole frame -- N = 1024 with the
-// register-resident decoder, N <= 512 with the generic decoder and its state
-// in the wavefront's LDS, and N >= 2048 with the generic decoder run by a
-// 256-thread workgroup that keeps L in its device-memory slot.  The last
-// group out of a kernel rewinds its counter, so the enqueued work needs no
-// host-side or memset reset and can be captured in a graph and replayed.
+// Two schedules, both a work queue of frames drained by persistent
+// wavefronts that each take the next entry from a device counter when they
+// finish a frame, and both decoding each frame exactly as pbp_decode does:
 //
-// Configuration: the order in which the code segments are drained (longest
-// code first or shortest first) and the number of resident wavefronts per
-// compute unit, set by the caller or chosen by timing the candidates on a
-// sample batch (pbp_mixed_plan_tune), with results cached per device, code
-// set and mode for the life of the process.
+// order 0 -- one launch for the whole batch, frames in the caller's order.
+//   One kernel dispatches on the frame's code length: N = 1024 frames run
+//   the register-resident decoder, N <= 512 the generic decoder with its
+//   state in the wavefront's LDS, N >= 2048 the generic decoder on one
+//   wavefront with L in that wavefront's device-memory slot.
+//
+// order 1 -- frames grouped by code, longest code first.  A device counting
+//   sort builds the queue (an order array of frame indices, one contiguous
+//   segment per code); each code's segment is then drained by a kernel
+//   specialised for its length, N >= 2048 by 256-thread workgroups that
+//   share one slot per frame.
+//
+// The last wavefront out of a launch rewinds its counters, so the enqueued
+// work needs no host-side or memset reset and can be captured in a graph and
+// replayed.  The order and the number of resident wavefronts per compute
+// unit are set by the caller or chosen by timing the candidates on a sample
+// batch (pbp_mixed_plan_tune), with results cached per device, code set and
+// mode for the life of the process.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -201,6 +206,159 @@ __global__ __launch_bounds__(kWgThreads, M >= 14 ? 2 : 4) void class_wg_kernel(C
     }
 }
 
+// ---- order 0: one persistent kernel for the whole batch ----
+
+struct MixedParams {
+    CodeDesc code[kMaxCodes];
+    int32_t ncodes;
+    const int32_t *code_of_frame;
+    const int64_t *llr_off;
+    const int64_t *info_off;
+    const float *llr;
+    int64_t B;
+    int32_t max_iter, early_stop, freezing, freeze_input, freeze_walk;
+    float alpha;
+    uint8_t *info_out;
+    int32_t *iters_out;
+    int64_t *pe_out;
+    int *counter;               // [queue head, waves out]
+    float *state;               // one slot per wavefront (long codes)
+    int64_t slot_floats;
+    int64_t *stats;             // per wavefront: start, end, busy (ticks)
+};
+
+// the generic decoder of code length 2^M on one wavefront (state in LDS up
+// to N = 512, in the wavefront's slot above 1024)
+template <int M>
+__device__ __forceinline__ void mixed_generic(const MixedParams &P,
+                                              const CodeDesc &cd, int f,
+                                              unsigned char *smem, float *slot,
+                                              int lane)
+{
+    DecodeParams D{};
+    D.llr = P.llr + P.llr_off[f];
+    D.B = 1;
+    D.frozen_words = cd.frozen_words;
+    D.info_pos = cd.info_pos;
+    D.K = cd.K;
+    D.max_iter = P.max_iter;
+    D.early_stop = P.early_stop;
+    D.freezing = P.freezing;
+    D.freeze_input = P.freeze_input;
+    D.freeze_walk = P.freeze_walk;
+    D.alpha = P.alpha;
+    D.info_out = P.info_out + P.info_off[f];
+    D.iters_out = P.iters_out + f;
+    D.pe_out = P.pe_out ? P.pe_out + f : nullptr;
+    D.soft_out = nullptr;
+    decode_frame<M, (M > pbp::kMaxLdsLog ? 1 : 0), true>(D, 0, smem, slot,
+                                                         lane, 64);
+}
+
+// ES: early stop (the register decoder's instantiation; the generic decoder
+// takes it at run time)
+template <bool ES>
+__global__ __launch_bounds__(64, 2) void mixed_kernel(MixedParams P)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int lane = (int)__builtin_amdgcn_workitem_id_x();
+    const int64_t wave = blockIdx.x;
+    float *slot = P.state ? P.state + wave * P.slot_floats : nullptr;
+    const int64_t t_start = wall_clock64();
+    int64_t busy = 0;
+    for (;;) {
+        int f = 0;
+        if (lane == 0)
+            f = atomicAdd(P.counter, 1);
+        f = __builtin_amdgcn_readfirstlane(__shfl(f, 0, 64));
+        if (f >= P.B)
+            break;
+        const int64_t t0 = wall_clock64();
+        const int c = __builtin_amdgcn_readfirstlane(P.code_of_frame[f]);
+        if (c < 0 || c >= P.ncodes) {
+            // a frame naming no code of the plan is not decoded
+            if (lane == 0) {
+                P.iters_out[f] = 0;
+                if (P.pe_out)
+                    P.pe_out[f] = 0;
+            }
+            continue;
+        }
+        const CodeDesc cd = P.code[c];
+        switch (cd.m) {
+        case pbp::r10::M: {
+            pbp::r10::Params R{};
+            R.llr = P.llr + P.llr_off[f];
+            R.B = 1;
+            R.fzw = cd.fzw10;
+            R.info_pos = cd.info_pos;
+            R.K = cd.K;
+            R.max_iter = P.max_iter;
+            R.freezing = P.freezing;
+            R.freeze_input = P.freeze_input;
+            R.freeze_walk = P.freeze_walk;
+            R.alpha = P.alpha;
+            R.info_out = P.info_out + P.info_off[f];
+            R.iters_out = P.iters_out + f;
+            R.pe_out = P.pe_out ? P.pe_out + f : nullptr;
+            R.soft_out = nullptr;
+            pbp::r10::Decoder<true, ES> D(
+                R, *reinterpret_cast<pbp::r10::Smem *>(smem), lane);
+            D.decode(0);
+            break;
+        }
+        case 1: mixed_generic<1>(P, cd, f, smem, slot, lane); break;
+        case 2: mixed_generic<2>(P, cd, f, smem, slot, lane); break;
+        case 3: mixed_generic<3>(P, cd, f, smem, slot, lane); break;
+        case 4: mixed_generic<4>(P, cd, f, smem, slot, lane); break;
+        case 5: mixed_generic<5>(P, cd, f, smem, slot, lane); break;
+        case 6: mixed_generic<6>(P, cd, f, smem, slot, lane); break;
+        case 7: mixed_generic<7>(P, cd, f, smem, slot, lane); break;
+        case 8: mixed_generic<8>(P, cd, f, smem, slot, lane); break;
+        case 9: mixed_generic<9>(P, cd, f, smem, slot, lane); break;
+        case 11: mixed_generic<11>(P, cd, f, smem, slot, lane); break;
+        case 12: mixed_generic<12>(P, cd, f, smem, slot, lane); break;
+        case 13: mixed_generic<13>(P, cd, f, smem, slot, lane); break;
+        case 14: mixed_generic<14>(P, cd, f, smem, slot, lane); break;
+        default: break;
+        }
+        busy += wall_clock64() - t0;
+    }
+    if (lane == 0) {
+        P.stats[wave * 3] = t_start;
+        P.stats[wave * 3 + 1] = wall_clock64();
+        P.stats[wave * 3 + 2] = busy;
+        // every wavefront has taken its last queue entry before it counts
+        // itself out; the last one out rewinds both counters
+        if (atomicAdd(P.counter + 1, 1) == (int)gridDim.x - 1) {
+            atomicExch(P.counter, 0);
+            atomicExch(P.counter + 1, 0);
+        }
+    }
+}
+
+// LDS of the single kernel for code length 2^m
+size_t mixed_lds(int m)
+{
+    switch (m) {
+    case 1: return pbp::generic::lds_bytes<1>(0);
+    case 2: return pbp::generic::lds_bytes<2>(0);
+    case 3: return pbp::generic::lds_bytes<3>(0);
+    case 4: return pbp::generic::lds_bytes<4>(0);
+    case 5: return pbp::generic::lds_bytes<5>(0);
+    case 6: return pbp::generic::lds_bytes<6>(0);
+    case 7: return pbp::generic::lds_bytes<7>(0);
+    case 8: return pbp::generic::lds_bytes<8>(0);
+    case 9: return pbp::generic::lds_bytes<9>(0);
+    case 10: return pbp::r10::smem_bytes();
+    case 11: return pbp::generic::lds_bytes<11>(1);
+    case 12: return pbp::generic::lds_bytes<12>(1);
+    case 13: return pbp::generic::lds_bytes<13>(1);
+    case 14: return pbp::generic::lds_bytes<14>(1);
+    default: return 0;
+    }
+}
+
 // ---- the work queue: frames grouped by code (counting sort) ----
 
 struct CodeSet {
@@ -208,18 +366,14 @@ struct CodeSet {
     int32_t ncodes;
 };
 
-// frame f's bucket: its code, or ncodes for a frame that is not decoded (a
-// code index outside the plan, or N = 1024 LLRs that are not 16-byte
-// aligned); such frames get zero iterations and PE updates here
+// frame f's bucket: its code, or ncodes for a frame that names no code of
+// the plan (not decoded: it gets zero iterations and PE updates here)
 __device__ __forceinline__ int bucket_of(const CodeSet &cs, const int32_t *code_of_frame,
                                          const int64_t *llr_off, const float *llr,
                                          int f)
 {
     const int c = code_of_frame[f];
     if (c < 0 || c >= cs.ncodes)
-        return cs.ncodes;
-    if (cs.m[c] == pbp::r10::M &&
-        (reinterpret_cast<uintptr_t>(llr + llr_off[f]) & 15))
         return cs.ncodes;
     return c;
 }
@@ -332,7 +486,10 @@ struct pbp_mixed_plan {
     float *d_state = nullptr;       // slots of long codes
     int64_t slot_floats = 0;
     int64_t *d_stats = nullptr;     // 3 per wavefront per code
-    int last_waves[kMaxCodes] = {};
+    int last_waves[kMaxCodes] = {};   // resident groups of each launch
+    int last_threads[kMaxCodes] = {}; // and their size
+    int last_launches = 0;            // launches of the last call
+    int64_t slots = 0;                // state slots (long codes)
     pbp_mixed_config cfg{0, 16};
 };
 
@@ -412,12 +569,70 @@ bool valid_cfg(const pbp_mixed_config *c)
            c->waves_per_cu <= kMaxWavesPerCu;
 }
 
+// order 0: the single persistent kernel over the batch in the caller's order
+hipError_t enqueue_single(pbp_mixed_plan *p, const pbp_mixed_config &cfg,
+                          const int32_t *code_of_frame, const int64_t *llr_off,
+                          const int64_t *info_off, int32_t B, const float *llr,
+                          const pbp_decode_opts *o, uint8_t *info_out,
+                          int32_t *iters_out, int64_t *pe_out, hipStream_t st)
+{
+    size_t lds = 0;
+    for (int c = 0; c < p->ncodes; c++)
+        lds = std::max(lds, mixed_lds(p->codes[c].m));
+    const void *kern = o->early_stop ? (const void *)mixed_kernel<true>
+                                     : (const void *)mixed_kernel<false>;
+    hipError_t e = hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)lds);
+    if (e != hipSuccess)
+        return e;
+    int per_cu = cfg.waves_per_cu;
+    int occ = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kern, 64, lds) ==
+            hipSuccess && occ >= 1 && occ < per_cu)
+        per_cu = occ;
+    int64_t grid = (int64_t)p->cus * per_cu;
+    if (p->slots > 0 && grid > p->slots)
+        grid = p->slots;
+    if (grid > B)
+        grid = B;
+    MixedParams P{};
+    for (int c = 0; c < p->ncodes; c++)
+        P.code[c] = p->codes[c];
+    P.ncodes = p->ncodes;
+    P.code_of_frame = code_of_frame;
+    P.llr_off = llr_off;
+    P.info_off = info_off;
+    P.llr = llr;
+    P.B = B;
+    P.max_iter = o->max_iter;
+    P.early_stop = o->early_stop;
+    P.freezing = o->freezing;
+    P.freeze_input = o->freeze_input;
+    P.freeze_walk = o->freeze_walk;
+    P.alpha = o->alpha;
+    P.info_out = info_out;
+    P.iters_out = iters_out;
+    P.pe_out = pe_out;
+    P.counter = p->d_counters;
+    P.state = p->d_state;
+    P.slot_floats = p->slot_floats;
+    P.stats = p->d_stats;
+    p->last_launches = 1;
+    p->last_waves[0] = (int)grid;
+    p->last_threads[0] = 64;
+    void *args[] = {&P};
+    return hipLaunchKernel(kern, dim3((unsigned)grid), dim3(64), args, lds, st);
+}
+
 hipError_t enqueue(pbp_mixed_plan *p, const pbp_mixed_config &cfg,
                    const int32_t *code_of_frame, const int64_t *llr_off,
                    const int64_t *info_off, int32_t B, const float *llr,
                    const pbp_decode_opts *o, uint8_t *info_out,
                    int32_t *iters_out, int64_t *pe_out, hipStream_t st)
 {
+    if (cfg.order == 0)
+        return enqueue_single(p, cfg, code_of_frame, llr_off, info_off, B, llr,
+                              o, info_out, iters_out, pe_out, st);
     const int nb = p->ncodes + 1;
     const int g = (int)std::min<int64_t>((B + 255) / 256, 4096);
     hipLaunchKernelGGL(clear_kernel, dim3(1), dim3(64), 0, st, p->d_cnt, nb);
@@ -431,15 +646,15 @@ hipError_t enqueue(pbp_mixed_plan *p, const pbp_mixed_config &cfg,
     hipError_t e = hipGetLastError();
     if (e != hipSuccess)
         return e;
-    // codes by decreasing (order 1) or increasing (order 0) length, stable
+    // codes by decreasing length, stable
     std::vector<int> seq(p->ncodes);
     for (int c = 0; c < p->ncodes; c++)
         seq[c] = c;
     std::stable_sort(seq.begin(), seq.end(), [&](int a, int b) {
-        return cfg.order == 1 ? p->codes[a].m > p->codes[b].m
-                              : p->codes[a].m < p->codes[b].m;
+        return p->codes[a].m > p->codes[b].m;
     });
     const int64_t max_waves = (int64_t)p->cus * kMaxWavesPerCu;
+    p->last_launches = 0;
     for (int c : seq) {
         const Launch L = class_launch(p->codes[c].m, o->early_stop);
         if (!L.kern)
@@ -482,6 +697,8 @@ hipError_t enqueue(pbp_mixed_plan *p, const pbp_mixed_config &cfg,
         P.slot_floats = p->slot_floats;
         P.stats = p->d_stats + (int64_t)c * max_waves * 3;
         p->last_waves[c] = (int)grid;
+        p->last_threads[c] = L.threads;
+        p->last_launches = p->ncodes;
         e = hipFuncSetAttribute(L.kern, hipFuncAttributeMaxDynamicSharedMemorySize,
                                 (int)L.lds);
         if (e != hipSuccess)
@@ -536,18 +753,21 @@ extern "C" int32_t pbp_mixed_plan_create(const pbp_code *const *codes,
         return PBP_EDEVICE;
     }
     const int64_t waves = (int64_t)p->cus * kMaxWavesPerCu;
-    const int64_t groups = (int64_t)p->cus * kMaxLongGroupsPerCu;
     int32_t st = PBP_OK;
-    // codes longer than 1024 keep L in a slot per resident workgroup
-    if (max_long)
+    // codes longer than 1024 keep L in a slot per resident workgroup: one
+    // per wavefront of the single kernel (order 0), which covers the
+    // 256-thread groups of the per-code kernels (order 1)
+    if (max_long) {
         p->slot_floats = (int64_t)(max_long + 1) << max_long;
+        p->slots = waves;
+    }
     if (hipMalloc(&p->d_counters, 2 * kMaxCodes * sizeof(int)) != hipSuccess ||
         hipMalloc(&p->d_cnt, (kMaxCodes + 1) * sizeof(int)) != hipSuccess ||
         hipMalloc(&p->d_bounds, (kMaxCodes + 2) * sizeof(int)) != hipSuccess ||
         hipMalloc(&p->d_cursor, (kMaxCodes + 1) * sizeof(int)) != hipSuccess ||
         hipMalloc(&p->d_order, max_frames * sizeof(int32_t)) != hipSuccess ||
         hipMalloc(&p->d_stats, ncodes * waves * 3 * sizeof(int64_t)) != hipSuccess ||
-        (max_long && hipMalloc(&p->d_state, groups * p->slot_floats *
+        (max_long && hipMalloc(&p->d_state, p->slots * p->slot_floats *
                                                 sizeof(float)) != hipSuccess))
         st = PBP_ENOMEM;
     else if (hipMemset(p->d_counters, 0, 2 * kMaxCodes * sizeof(int)) != hipSuccess ||
@@ -615,26 +835,31 @@ extern "C" int32_t pbp_mixed_plan_fill(pbp_mixed_plan *plan, void *stream,
         return PBP_EINVAL;
     if (hipStreamSynchronize((hipStream_t)stream) != hipSuccess)
         return PBP_EDEVICE;
+    // busy wavefront-time of every launch of the last call over (resident
+    // wavefronts x the call's whole span, from the first wavefront's start
+    // to the last one's end): kernel tails and the gaps between the
+    // per-code launches count as idle
     const int64_t max_waves = (int64_t)plan->cus * kMaxWavesPerCu;
-    double busy = 0.0, span = 0.0;
-    for (int c = 0; c < plan->ncodes; c++) {
+    double busy = 0.0;
+    int64_t t0 = INT64_MAX, t1 = INT64_MIN, cap = 0;
+    for (int c = 0; c < plan->last_launches; c++) {
         const int w = plan->last_waves[c];
         if (w <= 0)
             continue;
+        const int per = plan->last_threads[c] / 64;
         std::vector<int64_t> s((size_t)w * 3);
         if (hipMemcpy(s.data(), plan->d_stats + (int64_t)c * max_waves * 3,
                       s.size() * sizeof(int64_t),
                       hipMemcpyDeviceToHost) != hipSuccess)
             return PBP_EDEVICE;
-        int64_t t0 = s[0], t1 = s[1];
         for (int i = 0; i < w; i++) {
             t0 = std::min(t0, s[3 * i]);
             t1 = std::max(t1, s[3 * i + 1]);
-            busy += (double)s[3 * i + 2];
+            busy += (double)s[3 * i + 2] * per;
         }
-        span += (double)w * (double)(t1 - t0);
+        cap = std::max(cap, (int64_t)w * per);
     }
-    *fill = span > 0.0 ? busy / span : 0.0;
+    *fill = (cap > 0 && t1 > t0) ? busy / ((double)cap * (double)(t1 - t0)) : 0.0;
     return PBP_OK;
 }
 

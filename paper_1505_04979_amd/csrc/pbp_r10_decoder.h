@@ -266,17 +266,24 @@ struct Decoder {
     }
 
     // channel LLRs of a frame in mapping MA: register (qh, ql) of lane l is
-    // row 256 qh + 4 l + ql, so each lane reads four 16-byte vectors
+    // row 256 qh + 4 l + ql, so each lane reads four 16-byte vectors (four
+    // words each where the caller's buffer is not 16-byte aligned)
     __device__ __forceinline__ void load_channel(int64_t frame)
     {
         const float *src = P.llr + frame * N;
+        if (__builtin_expect((reinterpret_cast<uintptr_t>(src) & 15) == 0, 1)) {
 #pragma unroll
-        for (int qh = 0; qh < 4; qh++) {
-            const float4 v = *reinterpret_cast<const float4 *>(src + qh * 256 + lane * 4);
-            ch[qh * 4 + 0] = v.x;
-            ch[qh * 4 + 1] = v.y;
-            ch[qh * 4 + 2] = v.z;
-            ch[qh * 4 + 3] = v.w;
+            for (int qh = 0; qh < 4; qh++) {
+                const float4 v = *reinterpret_cast<const float4 *>(src + qh * 256 + lane * 4);
+                ch[qh * 4 + 0] = v.x;
+                ch[qh * 4 + 1] = v.y;
+                ch[qh * 4 + 2] = v.z;
+                ch[qh * 4 + 3] = v.w;
+            }
+        } else {
+#pragma unroll
+            for (int q = 0; q < Q; q++)
+                ch[q] = src[(q >> 2) * 256 + lane * 4 + (q & 3)];
         }
     }
 
@@ -768,8 +775,14 @@ struct Decoder {
                     const int r = row<MA>(q);
                     v[ql] = r < fm ? (S.dec[r] ? -kInf : kInf) : R[q] + l11(q, 0, 0);
                 }
-                *reinterpret_cast<float4 *>(so + qh * 256 + lane * 4) =
-                    make_float4(v[0], v[1], v[2], v[3]);
+                float *dst = so + qh * 256 + lane * 4;
+                if ((reinterpret_cast<uintptr_t>(so) & 15) == 0) {
+                    *reinterpret_cast<float4 *>(dst) = make_float4(v[0], v[1], v[2], v[3]);
+                } else {
+#pragma unroll
+                    for (int ql = 0; ql < 4; ql++)
+                        dst[ql] = v[ql];
+                }
             }
         }
         if (lane == 0) {

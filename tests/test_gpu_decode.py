@@ -211,10 +211,11 @@ def test_rejects_bad_arguments(env):
 
 @pytest.mark.parametrize("N,K,B", [(256, 128, 40), (1024, 512, 40),
                                    (4096, 2048, 6)])
-def test_unaligned_buffers_take_the_generic_kernel(env, N, K, B):
-    """LLRs at an address that is not 16-byte aligned: N = 1024 is decoded by
-    the generic kernel, and the generic kernel's first stage reads them one
-    PE at a time instead of in 16-byte groups, with the same results."""
+def test_unaligned_buffers(env, N, K, B):
+    """LLRs and posteriors at addresses that are not 16-byte aligned: the
+    N = 1024 register decoder reads and writes them by words instead of
+    16-byte vectors, and the generic kernel's first stage reads them one PE
+    at a time instead of in 16-byte groups, with the same results."""
     pbp, torch = env
     fz = frozen_mask(N, K)
     u, x, llr = make_frames(N, K, B, 2.5, stream=83)
@@ -223,8 +224,10 @@ def test_unaligned_buffers_take_the_generic_kernel(env, N, K, B):
     view = buf[1:].view(B, N)
     view.copy_(torch.from_numpy(llr))
     assert view.data_ptr() % 16 != 0
+    sbuf = torch.zeros(B * N + 3, dtype=torch.float32, device="cuda")
+    soft = sbuf[3:].view(B, N)
     kw = MODES["es_frz_total"]
-    o = pbp.pbp_decode(code, view, soft=True, **kw)
+    o = pbp.pbp_decode(code, view, soft=True, out={"soft": soft}, **kw)
     torch.cuda.synchronize()
     g = {k: v.cpu().numpy() for k, v in o.items()}
     r = oracle.decode(llr, fz, soft=True, **kw)
@@ -296,3 +299,23 @@ def test_graph_capture_replays(env, N, K, B):
         idx = np.arange(0, B, max(1, B // 6))
         r = oracle.decode(llr[idx], fz, soft=True, **kw)
         assert_parity({k: v[idx] for k, v in got.items()}, r, K, fz)
+
+
+@pytest.mark.parametrize("mode", ["es_frz_total", "es", "frz_total",
+                                  "es_frz_stage", "es_frz_r"])
+def test_long_code_converging_frames(env, mode):
+    """(16384, 8192) at 4.0 dB with 60 iterations: the frames converge (34
+    to 41 iterations on the oracle), so the m = 14 kernel's freezing walk,
+    its all-frozen exit and its early stop all act on noisy frames; bits,
+    iterations, PE counts and posteriors against the FP32 oracle."""
+    N, K = 16384, 8192
+    print(f"[decode] N={N} 4.0 dB mode={mode}", flush=True)
+    fz = frozen_mask(N, K)
+    u, _, llr = make_frames(N, K, 6, 4.0, stream=77)
+    g = gpu_decode(env, N, K, llr, max_iter=60, **MODES[mode])
+    r = oracle.decode(llr, fz, max_iter=60, soft=True, **MODES[mode])
+    assert_parity(g, r, K, fz)
+    if mode == "es_frz_total":
+        assert (r["iters"] < 60).all()
+        assert (r["pe"] < 60 * 7 * N).all()
+        assert np.array_equal(g["info"], u[:, fz == 0])

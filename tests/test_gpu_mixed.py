@@ -68,14 +68,18 @@ def oracle_check(dims, batch, out, mode, max_iter, frames=None):
         assert np.array_equal(pe[idx], r["pe"]), (N, K, mode)
 
 
+@pytest.mark.parametrize("order", [0, 1])
 @pytest.mark.parametrize("mode", list(MODES))
-def test_mixed_parity(env, mode):
+def test_mixed_parity(env, mode, order):
+    """Both schedules: one launch in the caller's order (0), one launch per
+    code after the device sort (1)."""
     pbp, torch = env
-    print(f"[mixed] mode={mode}", flush=True)
+    print(f"[mixed] mode={mode} order={order}", flush=True)
     dims = MIX
     batch = make_mixed(dims, 360, stream=40)
     cof, lo, io, llr, nbits = upload(torch, batch)
     plan = pbp.MixedPlan(codes_of(pbp, dims), 360)
+    plan.config = (order, 16)
     out = pbp.pbp_decode_mixed(plan, cof, lo, io, llr, info_bytes=nbits,
                                max_iter=60, alpha=0.9375, **MODES[mode])
     torch.cuda.synchronize()
@@ -99,9 +103,11 @@ def test_configs_give_identical_results(env, cfg):
     assert 0.0 < fill <= 1.0
 
 
-def test_frames_not_decoded(env):
-    """A frame naming no code of the plan, and an N = 1024 frame whose LLRs
-    are not 16-byte aligned, get zero iterations; the others decode."""
+@pytest.mark.parametrize("order", [0, 1])
+def test_frames_not_decoded(env, order):
+    """A frame naming no code of the plan gets zero iterations and is not
+    decoded; an N = 1024 frame whose LLRs are not 16-byte aligned decodes
+    like the others (the register decoder reads it by words)."""
     pbp, torch = env
     dims = [(256, 128), (1024, 512)]
     batch = make_mixed(dims, 40, stream=42)
@@ -118,13 +124,14 @@ def test_frames_not_decoded(env):
     lo[j] += 1
     d = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
     plan = pbp.MixedPlan(codes_of(pbp, dims), 40)
+    plan.config = (order, 16)
     out = pbp.pbp_decode_mixed(plan, d(cof), d(lo), d(io), d(big),
                                info_bytes=int(sum(len(i) for i in info)),
                                **MODES["es_frz"])
     torch.cuda.synchronize()
     it = out["iters"].cpu().numpy()
-    assert it[bad_code] == 0 and it[j] == 0
-    keep = [f for f in range(40) if f not in (bad_code, j)]
+    assert it[bad_code] == 0 and it[j] > 0
+    keep = [f for f in range(40) if f != bad_code]
     oracle_check(dims, (cof, ebn0, lo, io, big, info), out, "es_frz", 40,
                  frames=keep)
 
@@ -238,7 +245,7 @@ def test_full_size_mixed_batch_sampled(env):
     d_io = d(np.tile(io, REP) + k * nbits)
     d_llr = d(llr).repeat(REP)
     plan = pbp.MixedPlan(codes_of(pbp, MIX), B)
-    plan.config = (0, 16)
+    plan.config = (1, 16)
     out = pbp.pbp_decode_mixed(plan, d_cof, d_lo, d_io, d_llr,
                                info_bytes=nbits * REP, max_iter=60,
                                **MODES["es_frz"])
@@ -253,4 +260,6 @@ def test_full_size_mixed_batch_sampled(env):
                                         replace=False)
                              for c in range(len(MIX))])
     oracle_check(MIX, batch, first, "es_frz", 60, frames=frames)
-    assert 0.9 < pbp.pbp_mixed_plan_fill(plan) <= 1.0
+    fill = pbp.pbp_mixed_plan_fill(plan)
+    print(f"[mixed] fill {fill:.4f}", flush=True)
+    assert 0.5 < fill <= 1.0

@@ -104,6 +104,31 @@ def test_ranking_equals_literal_recursion_high_precision(N, K):
     assert gap is not None and gap > 1e-4
 
 
+@pytest.mark.parametrize("N,K,dps,gap_want", [
+    (4096, 1365, 2500, 9.560243e-4), (4096, 2048, 2500, 3.328686e-2),
+    (4096, 3413, 2500, 2.350008e-2), (16384, 8192, 8000, 2.259419e-3)])
+def test_long_code_ranking_equals_literal_recursion(N, K, dps, gap_want):
+    """The long codes of the mixed and long-code workloads: the literal
+    recursion on z alone, at enough digits that no z rounds to 1 (1 - z
+    reaches 1e-2243 at (4096, 1365) and 1e-6637 at (16384, 8192)), ranks
+    the positions as the oracle's logit recursion does; the boundary gap in
+    logits is recorded (the smallest of all configured codes is 9.6e-4)."""
+    m = N.bit_length() - 1
+    with mpmath.workdps(dps):
+        z0 = mpmath.exp(-mpmath.mpf(K) / N)
+        z = literal_recursion(m, z0)
+        assert min(1 - v for v in z) > 0
+        order = sorted(range(N), key=lambda i: (-z[i], i))
+        lo, hi = z[order[N - K - 1]], z[order[N - K]]
+        gap = float(mpmath.log(lo / (1 - lo)) - mpmath.log(hi / (1 - hi)))
+    want = np.zeros(N, np.uint8)
+    want[order[:N - K]] = 1
+    got, ogap = oracle.construct(N, K, 0.0)
+    assert np.array_equal(np.array(got, np.uint8), want)
+    assert abs(gap - gap_want) <= 1e-6 * gap_want
+    assert abs(ogap - gap) <= 1e-9 * gap
+
+
 def test_config_code_facts():
     fz, gap = oracle.construct(64, 32, 0.0)
     assert sum(fz) == 32
