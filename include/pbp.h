@@ -18,10 +18,17 @@
  *    favours 0.  Batches are row-major: frame f occupies [f*N, (f+1)*N).
  *  - "device" pointers are HIP device memory of the current device; "host"
  *    pointers are ordinary host memory.  The caller owns every buffer it
- *    passes; the library owns only pbp_code handles.
+ *    passes; the library owns pbp_code handles, mixed plans and the
+ *    per-stream decoder workspaces (see pbp_workspace_release).
  *  - `stream` is a hipStream_t (NULL: the default stream).  Device calls are
  *    asynchronous: they return after enqueuing, and results are valid once
  *    the stream has been synchronised.
+ *  - A pbp_code handle is immutable once created: any number of threads and
+ *    streams may use one handle at once.  Scratch that a decoder needs
+ *    between launches lives in a workspace the library keeps per (device,
+ *    stream), created by the first call on that stream that needs it (that
+ *    call allocates device memory and synchronises the device; later calls
+ *    on the stream do neither, unless a longer code needs more state).
  *  - Every call returns a pbp_status.  Arguments are checked on the host
  *    before anything is enqueued; a rejected call enqueues nothing.  No
  *    exception crosses the boundary.
@@ -43,7 +50,8 @@ typedef enum {
     PBP_EUNSUPPORTED = -4   /* valid request this build does not handle    */
 } pbp_status;
 
-/* Opaque, immutable code handle: N, K, the frozen set and its device copy. */
+/* Opaque, immutable code handle: N, K, the frozen set, its device copy and
+ * the launch geometry derived from them. */
 typedef struct pbp_code pbp_code;
 
 /* Decoder options.
@@ -119,27 +127,37 @@ int32_t pbp_encode(const pbp_code *code, const uint8_t *info, int64_t B,
  *             computation count), or NULL
  *   soft_out  device, B x N FP32, or NULL: the posterior LLR of each source
  *             bit at exit (R + L at column m+1; +-inf inside frozen CSFGs)
- * A handle holds per-call device state (the frame counter of the persistent
- * kernels, the message state of codes longer than 1024): calls on one handle
- * must be ordered on one stream, never in flight on two streams at once.
- * Errors: PBP_EINVAL (bad options, B < 0, NULL required pointer),
+ * The frame counter of the persistent kernels and the message state of codes
+ * longer than 1024 come from the stream's workspace (see the conventions
+ * above), so calls on different streams may overlap, on one handle or
+ * several.  The message state takes (m + 1) N floats per resident
+ * workgroup: 503 MB on 256 compute units at N = 16384.
+ * Errors: PBP_EINVAL (bad options, B < 0, NULL required pointer; checked
+ * before any allocation), PBP_ENOMEM (the workspace cannot be allocated),
  * PBP_EDEVICE (launch failure). */
 int32_t pbp_decode(const pbp_code *code, const float *llr, int64_t B,
                    const pbp_decode_opts *opts, uint8_t *info_out,
                    int32_t *iters_out, int64_t *pe_out, float *soft_out,
                    void *stream);
 
+/* Free the decoder workspace of `stream` on the current device, after
+ * synchronising that stream (a no-op when it has none).  The next decode on
+ * the stream creates a new one.  Call it before destroying a stream that
+ * decoded, so that a later stream created at the same address starts clean.
+ * Errors: PBP_EDEVICE. */
+int32_t pbp_workspace_release(void *stream);
+
 /* pbp_decode for callers that cannot allocate device memory (code under
  * graph capture, tight serving loops, harnesses that forbid hipMalloc):
  * the same decoding, arguments and results bit for bit, with the scratch of
  * the persistent kernels (the N = 1024 kernel's frame counter, the message
  * state of codes longer than 1024) taken from a static 64 MiB device array
- * instead of the handle, and no allocation of any kind.  Each GPU holds one
- * such array until the process ends; codes longer than 1024 run at most as
- * many resident workgroups as state slots fit in it (683 at N = 2048, 315 at
- * N = 4096, 68 at N = 16384).  Every call on a GPU shares that array, so
- * calls that overlap on one GPU (two streams, or two threads) race; order
- * them on one stream.  B must be at most 2^30.
+ * instead of the stream's workspace, and no allocation of any kind.  Each
+ * GPU holds one such array until the process ends; codes longer than 1024
+ * run at most as many resident workgroups as state slots fit in it (683 at
+ * N = 2048, 315 at N = 4096, 68 at N = 16384).  Every call on a GPU shares
+ * that array, so calls that overlap on one GPU (two streams, or two
+ * threads) race; order them on one stream.  B must be at most 2^30.
  * Errors: as pbp_decode; PBP_EINVAL also for B > 2^30, PBP_EDEVICE when the
  * array's address cannot be obtained. */
 int32_t pbp_decode_noalloc(const pbp_code *code, const float *llr, int64_t B,
@@ -153,8 +171,9 @@ int32_t pbp_decode_noalloc(const pbp_code *code, const float *llr, int64_t B,
  * just computed at column j+1 and the previous pass's R at column j), then
  * every R output for stages 1, ..., m (from the R just computed at column j
  * and this pass's L at column j+1).  Arguments, layouts, ownership and the
- * stop test as for pbp_decode; pe_out counts both passes, m N PE
- * activations per iteration.  opts->freezing must be 0 and N <= 2048.
+ * stop test as for pbp_decode (its frame counter also comes from the
+ * stream's workspace); pe_out counts both passes, m N PE activations per
+ * iteration.  opts->freezing must be 0 and N <= 2048.
  * Errors: as pbp_decode; PBP_EUNSUPPORTED for freezing or N > 2048. */
 int32_t pbp_decode_round_trip(const pbp_code *code, const float *llr,
                               int64_t B, const pbp_decode_opts *opts,

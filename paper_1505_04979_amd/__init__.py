@@ -15,5 +15,5 @@ from .binding import (Code, MixedPlan, PbpError, exported_symbols, lib,  # noqa
                       pbp_encode, pbp_mixed_config, pbp_mixed_plan_create,
                       pbp_mixed_plan_fill, pbp_mixed_plan_tune,
                       pbp_unrolled_backward, pbp_unrolled_forward,
-                      status_string)
+                      pbp_workspace_release, status_string)
 from .unrolled import UnrolledBP, info_bce, unrolled_bp  # noqa

@@ -54,6 +54,7 @@ _SIGNATURES = [
     ("pbp_decode_noalloc", ctypes.c_int32,
      [_P, _P, ctypes.c_int64, ctypes.POINTER(pbp_decode_opts), _P, _P, _P, _P,
       _P]),
+    ("pbp_workspace_release", ctypes.c_int32, [_P]),
     ("pbp_decode_round_trip", ctypes.c_int32,
      [_P, _P, ctypes.c_int64, ctypes.POINTER(pbp_decode_opts), _P, _P, _P, _P,
       _P]),
@@ -265,6 +266,13 @@ def pbp_decode_noalloc(code, llr, opts=None, pe=True, soft=False, out=None,
     arguments and outputs.  Pass ``out`` to allocate nothing here either."""
     return pbp_decode(code, llr, opts=opts, pe=pe, soft=soft, out=out,
                       stream=stream, schedule="noalloc", **kw)
+
+
+def pbp_workspace_release(stream=None):
+    """Free the library's decoder workspace of ``stream`` (default: torch's
+    current stream) on the current device, after synchronising it."""
+    _check("pbp_workspace_release", lib().pbp_workspace_release(
+        _stream(stream)))
 
 
 def pbp_decode_quant(code, llr, bits=8, frac=3, opts=None, pe=True, soft=False,

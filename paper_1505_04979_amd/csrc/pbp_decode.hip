@@ -120,6 +120,8 @@ struct Scratch {
     int64_t slots;
 };
 
+// sc == nullptr: check the arguments only, enqueue nothing
+
 int32_t decode_impl(const pbp_code *code, const float *llr, int64_t B,
                     const pbp_decode_opts *opts, uint8_t *info_out,
                     int32_t *iters_out, int64_t *pe_out, float *soft_out,
@@ -137,6 +139,8 @@ int32_t decode_impl(const pbp_code *code, const float *llr, int64_t B,
         return PBP_OK;
     if (!llr || !iters_out || (!info_out && code->K > 0))
         return PBP_EINVAL;
+    if (!sc)            // arguments checked, nothing to enqueue
+        return PBP_OK;
     DecodeParams P{};
     P.llr = llr;
     P.B = B;
@@ -191,7 +195,16 @@ extern "C" int32_t pbp_decode(const pbp_code *code, const float *llr, int64_t B,
 {
     if (!code)
         return PBP_EINVAL;
-    const Scratch sc{code->d_counter, code->d_state, code->state_slots};
+    // argument errors first: a rejected call allocates nothing either
+    const int32_t chk = decode_impl(code, llr, B, opts, info_out, iters_out,
+                                    pe_out, soft_out, stream, nullptr);
+    if (chk != PBP_OK || B == 0)
+        return chk;
+    pbp::Workspace ws;
+    const int32_t st = pbp::stream_workspace(code, (hipStream_t)stream, &ws);
+    if (st != PBP_OK)
+        return st;
+    const Scratch sc{ws.counter, ws.state, code->state_slots};
     return decode_impl(code, llr, B, opts, info_out, iters_out, pe_out,
                        soft_out, stream, &sc);
 }

@@ -3,8 +3,12 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdint>
+#include <map>
+#include <mutex>
 #include <new>
 #include <numeric>
+#include <utility>
 #include <vector>
 
 #include "pbp_internal.h"
@@ -78,10 +82,6 @@ void free_code(pbp_code *c)
         (void)hipFree(c->d_frozen_words);
     if (c->d_info_pos)
         (void)hipFree(c->d_info_pos);
-    if (c->d_state)
-        (void)hipFree(c->d_state);
-    if (c->d_counter)
-        (void)hipFree(c->d_counter);
     if (c->d_fzw10)
         (void)hipFree(c->d_fzw10);
     delete c;
@@ -149,16 +149,6 @@ extern "C" int32_t pbp_code_create(int32_t N, int32_t K, const uint8_t *frozen,
         free_code(c);
         return PBP_EDEVICE;
     }
-    // frame counter and exit counter of the persistent kernels: zero here,
-    // and rewound to zero by the last wave of each launch
-    if (hipMalloc(&c->d_counter, 2 * sizeof(int)) != hipSuccess) {
-        free_code(c);
-        return PBP_ENOMEM;
-    }
-    if (hipMemset(c->d_counter, 0, 2 * sizeof(int)) != hipSuccess) {
-        free_code(c);
-        return PBP_EDEVICE;
-    }
     if (c->m == pbp::r10::M) {
         uint64_t fzw[4 * pbp::r10::Q];
         pbp::r10::frozen_words(c->frozen.data(), fzw);
@@ -174,19 +164,15 @@ extern "C" int32_t pbp_code_create(int32_t N, int32_t K, const uint8_t *frozen,
     }
     if (c->m > pbp::kMaxLdsLog) {
         // message state of codes too long for LDS: one slot per resident
-        // workgroup, (m + 1) columns of N floats each.  The workgroups hold
-        // the working R column and two bit words per 64 rows in LDS, so as
-        // many as fit in 160 KB (at most 4) are resident per compute unit.
+        // workgroup, (m + 1) columns of N floats each, in the workspace of
+        // the decoding stream.  The workgroups hold the working R column and
+        // two bit words per 64 rows in LDS, so as many as fit in 160 KB (at
+        // most 4) are resident per compute unit.
         const int64_t lds = 4 * (int64_t)N + 16 * (int64_t)(N / 64) + 128;
         int64_t per_cu = (160 * 1024) / lds;
         per_cu = per_cu < 1 ? 1 : (per_cu > 4 ? 4 : per_cu);
         c->state_slots = (int64_t)c->cus * per_cu;
         c->state_floats_per_slot = (int64_t)(c->m + 1) * N;
-        if (hipMalloc(&c->d_state, sizeof(float) * c->state_slots *
-                                       c->state_floats_per_slot) != hipSuccess) {
-            free_code(c);
-            return PBP_ENOMEM;
-        }
     }
     *out = c;
     return PBP_OK;
@@ -204,6 +190,101 @@ extern "C" void pbp_code_destroy(pbp_code *code)
     free_code(code);
     if (prev != dev)
         (void)hipSetDevice(prev);
+}
+
+// ---- Per-stream workspaces -------------------------------------------------
+
+namespace {
+
+struct WsEntry {
+    int *counter = nullptr;
+    float *state = nullptr;
+    int64_t state_floats = 0;   // capacity of state
+};
+
+std::mutex g_ws_mu;
+std::map<std::pair<int, uintptr_t>, WsEntry> g_ws;
+
+// Run fn with `dev` current, restoring the caller's device afterwards.
+template <class Fn>
+int32_t on_device(int dev, Fn fn)
+{
+    int prev = -1;
+    if (hipGetDevice(&prev) != hipSuccess)
+        return PBP_EDEVICE;
+    if (prev != dev && hipSetDevice(dev) != hipSuccess)
+        return PBP_EDEVICE;
+    const int32_t st = fn();
+    if (prev != dev)
+        (void)hipSetDevice(prev);
+    return st;
+}
+
+}  // namespace
+
+int32_t pbp::stream_workspace(const pbp_code *code, hipStream_t stream,
+                              Workspace *out)
+{
+    const int64_t need = code->state_slots * code->state_floats_per_slot;
+    std::lock_guard<std::mutex> lock(g_ws_mu);
+    WsEntry *e;
+    try {
+        e = &g_ws[{code->device, reinterpret_cast<uintptr_t>(stream)}];
+    } catch (const std::bad_alloc &) {
+        return PBP_ENOMEM;
+    }
+    const int32_t st = on_device(code->device, [&]() -> int32_t {
+        if (!e->counter) {
+            // zero here; each persistent launch's last wave rewinds it
+            if (hipMalloc(&e->counter, 2 * sizeof(int)) != hipSuccess) {
+                e->counter = nullptr;
+                return PBP_ENOMEM;
+            }
+            if (hipMemset(e->counter, 0, 2 * sizeof(int)) != hipSuccess ||
+                hipDeviceSynchronize() != hipSuccess)
+                return PBP_EDEVICE;
+        }
+        if (need > e->state_floats) {
+            // earlier calls on this stream may still read the old slots
+            if (e->state) {
+                if (hipStreamSynchronize(stream) != hipSuccess)
+                    return PBP_EDEVICE;
+                (void)hipFree(e->state);
+                e->state = nullptr;
+                e->state_floats = 0;
+            }
+            if (hipMalloc(&e->state, sizeof(float) * need) != hipSuccess) {
+                e->state = nullptr;
+                return PBP_ENOMEM;
+            }
+            e->state_floats = need;
+        }
+        return PBP_OK;
+    });
+    if (st != PBP_OK)
+        return st;
+    out->counter = e->counter;
+    out->state = e->state;
+    return PBP_OK;
+}
+
+extern "C" int32_t pbp_workspace_release(void *stream)
+{
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess)
+        return PBP_EDEVICE;
+    std::lock_guard<std::mutex> lock(g_ws_mu);
+    auto it = g_ws.find({dev, reinterpret_cast<uintptr_t>(stream)});
+    if (it == g_ws.end())
+        return PBP_OK;
+    if (hipStreamSynchronize((hipStream_t)stream) != hipSuccess)
+        return PBP_EDEVICE;
+    if (it->second.counter)
+        (void)hipFree(it->second.counter);
+    if (it->second.state)
+        (void)hipFree(it->second.state);
+    g_ws.erase(it);
+    return PBP_OK;
 }
 
 extern "C" int32_t pbp_code_dims(const pbp_code *code, int32_t *N, int32_t *K)

@@ -17,12 +17,9 @@ struct pbp_code {
     uint64_t *d_frozen_words = nullptr;  // device, frozen bit mask, row i is
                                          // bit (i & 63) of word i >> 6
     int32_t *d_info_pos = nullptr;     // device, K entries (at least 1)
-    float *d_state = nullptr;          // device message state for codes whose
-    int64_t state_slots = 0;           // state does not fit in LDS
-    int64_t state_floats_per_slot = 0;
+    int64_t state_slots = 0;           // message-state slots of codes whose
+    int64_t state_floats_per_slot = 0; // state does not fit in LDS
     int cus = 0;                       // compute units of the device
-    int *d_counter = nullptr;          // [frame, exit] counters of persistent
-                                       // kernels, zero between launches
     uint64_t *d_fzw10 = nullptr;       // N = 1024: frozen ballot words [4][16]
 };
 
@@ -43,5 +40,20 @@ inline int log2i(int32_t N)
 
 // Largest code length whose full message state lives in LDS.
 constexpr int kMaxLdsLog = 10;
+
+// Device scratch of the decoders on one (device, stream): the [frame, exit]
+// counters of the persistent kernels (zero between launches) and the
+// message-state slots of codes longer than 1024.  Owned by the library, not
+// the code handle, so that one handle serves several streams at once.
+struct Workspace {
+    int *counter = nullptr;
+    float *state = nullptr;
+};
+
+// The workspace of `stream` on the handle's device, created on first use and
+// grown (after synchronising that stream) when a longer code needs more
+// state.  Calls on one stream are ordered, so they share it safely.
+int32_t stream_workspace(const pbp_code *code, hipStream_t stream,
+                         Workspace *out);
 
 }  // namespace pbp

@@ -112,7 +112,7 @@ __global__ __launch_bounds__(RtShape<M>::NT, 8) void bp_round_trip_kernel(RtPara
     // and 2 t + 1), read once for the launch
     const int fz_m = act ? (int)(frozen_at(2 * tid) | (frozen_at(2 * tid + 1) << 1)) : 0;
 
-    // Frames come from the handle's device counter, so that groups whose
+    // Frames come from the stream workspace's counter, so that groups whose
     // frames stop early take more of them; the counter numbers frames in 32
     // bits, so batches beyond 2^30 frames are split by grid stride instead.
     __shared__ int64_t next;
@@ -319,7 +319,13 @@ extern "C" int32_t pbp_decode_round_trip(const pbp_code *code, const float *llr,
     P.iters_out = iters_out;
     P.pe_out = pe_out;
     P.soft_out = soft_out;
-    P.counter = B <= (int64_t(1) << 30) ? code->d_counter : nullptr;
+    if (B <= (int64_t(1) << 30)) {
+        pbp::Workspace ws;
+        const int32_t wst = pbp::stream_workspace(code, (hipStream_t)stream, &ws);
+        if (wst != PBP_OK)
+            return wst;
+        P.counter = ws.counter;
+    }
     hipStream_t st = (hipStream_t)stream;
     hipError_t e;
     switch (code->m) {

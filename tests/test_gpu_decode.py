@@ -319,3 +319,45 @@ def test_long_code_converging_frames(env, mode):
         assert (r["iters"] < 60).all()
         assert (r["pe"] < 60 * 7 * N).all()
         assert np.array_equal(g["info"], u[:, fz == 0])
+
+
+@pytest.mark.parametrize("N,K,B", [(1024, 512, 4096), (4096, 2048, 384)])
+def test_one_handle_on_two_streams(env, N, K, B):
+    """One handle decoding on two streams at once: each stream has its own
+    workspace (the persistent kernel's frame counter, the long-code state
+    slots), so overlapping decodes equal the same decodes made one after the
+    other, repeat after repeat, and the oracle on sampled frames."""
+    pbp, torch = env
+    print(f"[decode] two streams N={N} B={B}", flush=True)
+    fz = frozen_mask(N, K)
+    code = code_of(pbp, N, K)
+    kw = MODES["es_frz_total"]
+    _, _, l1 = make_frames(N, K, B, 2.5, stream=131)
+    _, _, l2 = make_frames(N, K, B, 3.0, stream=132)
+    d1, d2 = torch.from_numpy(l1).cuda(), torch.from_numpy(l2).cuda()
+    ref1 = pbp.pbp_decode(code, d1, soft=True, **kw)
+    ref2 = pbp.pbp_decode(code, d2, soft=True, **kw)
+    torch.cuda.synchronize()
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    for rep in range(3):
+        with torch.cuda.stream(s1):
+            o1 = pbp.pbp_decode(code, d1, soft=True, stream=s1, **kw)
+        with torch.cuda.stream(s2):
+            o2 = pbp.pbp_decode(code, d2, soft=True, stream=s2, **kw)
+        torch.cuda.synchronize()
+        for o, ref in ((o1, ref1), (o2, ref2)):
+            for k in ref:
+                assert torch.equal(o[k], ref[k]), (rep, k)
+    idx = np.arange(0, B, B // 8)
+    for llr, o in ((l1, o1), (l2, o2)):
+        r = oracle.decode(llr[idx], fz, soft=True, **kw)
+        assert_parity({k: v.cpu().numpy()[idx] for k, v in o.items()}, r, K,
+                      fz)
+    pbp.pbp_workspace_release(s1)
+    pbp.pbp_workspace_release(s2)
+    # a released stream gets a fresh workspace on its next decode
+    with torch.cuda.stream(s1):
+        o1 = pbp.pbp_decode(code, d1, soft=True, stream=s1, **kw)
+    torch.cuda.synchronize()
+    for k in ref1:
+        assert torch.equal(o1[k], ref1[k]), k
