@@ -73,6 +73,8 @@ def _lib(prec):
         lib.oracle_csfg_check.restype = ctypes.c_int
         lib.oracle_unrolled_forward.argtypes = [ctypes.c_int, P, ctypes.c_int64,
                                                 P, ctypes.c_int, P, P]
+        lib.oracle_unrolled_messages.argtypes = [
+            ctypes.c_int, P, ctypes.c_int64, P, ctypes.c_int, P, P, P]
         lib.oracle_unrolled_grad.argtypes = [ctypes.c_int, P, ctypes.c_int64,
                                              P, ctypes.c_int, P, P, P, P]
         lib.oracle_unrolled_grad_mag.argtypes = \
@@ -184,6 +186,24 @@ def unrolled_forward(llr, frozen, alpha, prec="f64"):
     _lib(prec).oracle_unrolled_forward(m, _ptr(frozen), B, _ptr(llr), T,
                                        _ptr(alpha), _ptr(out))
     return out
+
+
+def unrolled_messages(llr, frozen, alpha, prec="f64"):
+    """Every message of the unrolled decoder: (L, R), each (B, T+1, m+2, N),
+    column c of iteration t at [f, t, c] (t = 0: the initial state; column 0
+    unused).  Section II-A, eq. (1), applied as in unrolled_forward."""
+    llr = np.ascontiguousarray(llr, dtype=np.float32)
+    B, N = llr.shape
+    m = _m_of(N)
+    alpha = np.ascontiguousarray(alpha, dtype=np.float64)
+    T = alpha.shape[0]
+    assert alpha.shape == (T, m, 2)
+    frozen = np.ascontiguousarray(frozen, dtype=np.uint8)
+    L = np.empty((B, T + 1, m + 2, N), _real(prec))
+    R = np.empty_like(L)
+    _lib(prec).oracle_unrolled_messages(m, _ptr(frozen), B, _ptr(llr), T,
+                                        _ptr(alpha), _ptr(L), _ptr(R))
+    return L, R
 
 
 def unrolled_grad(llr, frozen, alpha, dout, prec="f64"):

@@ -385,6 +385,23 @@ int oracle_unrolled_forward(int m, const uint8_t *frozen, int64_t B,
     return 0;
 }
 
+/* Every message of the forward: L and R, each B x (T+1) x (m+2) x n, hold
+ * column c of iteration t at [f][t][c][i] (t = 0 is the initial state;
+ * column 0 is unused).  Returns 0, or -1 on bad arguments. */
+int oracle_unrolled_messages(int m, const uint8_t *frozen, int64_t B,
+                             const float *llr, int T, const double *alpha,
+                             real *L, real *R)
+{
+    if (m < 1 || m > 16 || B < 0 || T < 1)
+        return -1;
+    const int n = 1 << m;
+    const size_t per = (size_t)(m + 2) * n * (T + 1);
+    for (int64_t f = 0; f < B; f++)
+        unrolled_fwd_frame(m, frozen, llr + f * n, T, alpha, L + f * per,
+                           R + f * per);
+    return 0;
+}
+
 /* Route the adjoint d of g0(x, y) to x or y (see above); an infinite
  * operand takes nothing.  With mag set, the sign factor is dropped (see
  * unrolled_grad_core). */

@@ -252,3 +252,34 @@ def test_rejects_bad_arguments(env):
         code, torch.zeros((0, 64), dtype=torch.float32, device="cuda"),
         torch.ones((2, 6, 2), dtype=torch.float32, device="cuda"), ckpt=False)
     assert out.shape == (0, 64)
+
+
+@pytest.mark.parametrize("N,K,T,B", [(8, 4, 3, 30), (64, 32, 5, 20),
+                                     (1024, 512, 6, 4)])
+def test_intermediate_messages(env, N, K, T, B):
+    """The L messages the forward checkpoints (columns 2..m at the start of
+    every iteration) against the FP32 oracle's, element by element at every
+    (iteration, column, row): the same operation order gives the same
+    values, so they are compared for equality, inside the 1e-5 relative bar
+    everywhere; infinite (frozen) messages compare as infinities."""
+    pbp, torch = env
+    print(f"[unrolled] messages N={N} T={T} B={B}", flush=True)
+    m = N.bit_length() - 1
+    fz = frozen_mask(N, K)
+    _, _, llr = make_frames(N, K, B, 2.0, stream=600 + N)
+    rng = np.random.default_rng(N + 7)
+    alpha = rng.uniform(0.6, 1.1, size=(T, m, 2)).astype(np.float32)
+    code = code_of(pbp, N, K)
+    _, ck = pbp.pbp_unrolled_forward(code, torch.from_numpy(llr).cuda(),
+                                     torch.from_numpy(alpha).cuda())
+    torch.cuda.synchronize()
+    ck = ck.cpu().numpy()                                  # (T, B, m-1, N)
+    L, _ = oracle.unrolled_messages(llr, fz, alpha.astype(np.float64),
+                                    prec="f32")
+    ref = L[:, :T, 2:m + 1].transpose(1, 0, 2, 3)          # (T, B, m-1, N)
+    assert ck.shape == ref.shape
+    bad = ck != ref
+    assert not bad.any(), np.argwhere(bad)[:5]
+    fin = np.isfinite(ref)
+    rel = np.abs(ck[fin] - ref[fin]) / np.maximum(np.abs(ref[fin]), 1e-30)
+    assert rel.max(initial=0.0) <= 1e-5

@@ -154,3 +154,74 @@ def test_magnitude_sums_n2_closed_form_and_bound():
     Aa, Al = oracle.unrolled_grad_mag(pos, fz, alpha, dpos)
     assert np.allclose(Aa, da, rtol=1e-12, atol=0)
     assert np.allclose(Al, dl, rtol=1e-12, atol=0)
+
+
+def test_messages_n2_closed_forms():
+    """Every message of the N = 2 graph, iteration by iteration: with the
+    frozen prior +inf at row 0 and 0 at row 1, L(column 1) = (aL y1, aL y0),
+    R(column 2) = (aR g(y0, y1), y1 + aR y0), g(x, y) = sign(x) sign(y)
+    min(|x|, |y|); the channel column and the prior column never change."""
+    rng = np.random.default_rng(11)
+    y = (rng.standard_normal((40, 2)) * 2).astype(np.float32)
+    fz = np.array([1, 0], np.uint8)
+    T = 3
+    alpha = rng.uniform(0.5, 1.2, size=(T, 1, 2))
+    L, R = oracle.unrolled_messages(y, fz, alpha)
+    y0, y1 = y[:, 0].astype(np.float64), y[:, 1].astype(np.float64)
+    g = np.sign(y0) * np.sign(y1) * np.minimum(np.abs(y0), np.abs(y1))
+    # the initial state: zeros but for the prior column
+    assert np.all(L[:, 0, :2] == 0) and np.all(R[:, 0] == 0)
+    assert np.all(L[:, 0, 2, 0] == np.inf) and np.all(L[:, 0, 2, 1] == 0)
+    for t in range(1, T + 1):
+        aL, aR = alpha[t - 1, 0]
+        assert np.all(L[:, t, 2, 0] == np.inf) and np.all(L[:, t, 2, 1] == 0)
+        assert np.array_equal(R[:, t, 1], y.astype(np.float64))
+        assert np.allclose(L[:, t, 1, 0], aL * y1, rtol=1e-15, atol=0)
+        assert np.allclose(L[:, t, 1, 1], aL * y0, rtol=1e-15, atol=0)
+        assert np.allclose(R[:, t, 2, 0], aR * g, rtol=1e-15, atol=0)
+        assert np.allclose(R[:, t, 2, 1], y1 + aR * y0, rtol=1e-15, atol=0)
+
+
+def _column_bits(u):
+    """Bits carried at every column of the graph for source words u (B, N):
+    column m+1 holds u; stage j maps column j+1 to column j by
+    v_j[a] = v_{j+1}[a] ^ v_{j+1}[a + h], v_j[a + h] = v_{j+1}[a + h] with
+    h = N / 2^j, so column 1 holds the codeword."""
+    B, N = u.shape
+    m = N.bit_length() - 1
+    v = np.zeros((B, m + 2, N), np.uint8)
+    v[:, m + 1] = u
+    for j in range(m, 0, -1):
+        h = N >> j
+        v[:, j] = v[:, j + 1]
+        for a in range(N):
+            if not a & h:
+                v[:, j, a] ^= v[:, j + 1, a + h]
+    return v
+
+
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+@pytest.mark.parametrize("N,K,T", [(8, 4, 3), (64, 32, 4), (256, 128, 3)])
+def test_messages_follow_codeword_symmetry(prec, N, K, T):
+    """Flipping the channel LLRs by a codeword x = u G flips every message at
+    column c, row i, by the bit the graph carries there (eq. (1) is odd in
+    each operand and the frozen bits of u are 0), exactly, in every
+    iteration; the last column's R equals the forward's output."""
+    m = N.bit_length() - 1
+    fz = frozen_mask(N, K)
+    rng = np.random.default_rng(N)
+    _, _, llr = make_frames(N, K, 6, 1.5, stream=72)
+    u = np.zeros((6, N), np.uint8)
+    u[:, fz == 0] = rng.integers(0, 2, size=(6, K))
+    v = _column_bits(u)
+    x = v[:, 1]
+    assert np.array_equal(x, oracle.encode(u))
+    alpha = rng.uniform(0.7, 1.1, size=(T, m, 2))
+    L0, R0 = oracle.unrolled_messages(llr, fz, alpha, prec=prec)
+    flip = llr * (1 - 2 * x.astype(np.float32))
+    L1, R1 = oracle.unrolled_messages(flip, fz, alpha, prec=prec)
+    s = (1 - 2 * v.astype(np.float64))[:, None]          # (B, 1, m+2, N)
+    assert np.array_equal(L1, L0 * s)
+    assert np.array_equal(R1, R0 * s)
+    out = oracle.unrolled_forward(llr, fz, alpha, prec=prec)
+    assert np.array_equal(R0[:, T, m + 1], out)
