@@ -30,13 +30,14 @@ METRIC = ("decoded info Mbit/s at N=1024 R=1/2 3.0dB, FER-matched; "
 # FP32 VALU roofline of gfx950 without packed FP32: 256 CUs x 4 SIMDs x 16
 # lanes x 2.4 GHz FP32 lane operations per second (the published FP64 vector
 # rate, 78.6 TFLOP/s, is these lanes at two flops per FMA; the published FP32
-# figure counts packed FP32, which these kernels do not use).  Eq. (1) costs
-# 9 FP32 operations per PE activation: 3 adds, 3 magnitude minima (one median
-# of three each) and 3 scalings.  Its 3 sign products are one 3-input bitwise
-# operation each, which gfx950 issues beside the FP32 work: a chain of
-# median + scaling + bitwise op runs 1.45x the FP32-only lane rate.
+# figure counts packed FP32, which these kernels do not use).
 VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
-OPS_PER_PE = 9
+# Algorithmic work of one PE activation of eq. (1): three distinct min-sum
+# terms (each a sign product, a magnitude minimum and a scaling) and three
+# additions, 12 operations.  gfx950 issues about 11 VALU instructions for
+# them (a median of three is the clamped minimum and carries one sign), so
+# the kernel's issued-instruction rate is reported beside this fraction.
+OPS_PER_PE = 12
 
 # the kernel one step launches (one launch per step)
 KERNEL = "bp_decode_r10_kernel<true, true>"
@@ -61,6 +62,24 @@ TRAFFIC_RECORDS = {
               _csrc("pbp_mixed.hip", "pbp_generic_decoder.h")),
 }
 KERNEL_SRCS = TRAFFIC_RECORDS["n1024"][1]
+
+# Kernel-trace summaries (rocprofv3 --kernel-trace --stats of the workload's
+# own bench command): the roofline kernel's average dispatch duration, valid
+# while its sources are unchanged; plus, for the headline, the VALU
+# instructions the counters run issued per launch.
+TRACE_RECORDS = {
+    "n1024": ("bp_decode_r10_n1024_3db_trace.md", KERNEL_SRCS),
+    "c1": ("bp_decode_n64_c1_trace.md",
+           _csrc("pbp_decode.hip", "pbp_generic_decoder.h")),
+    "n16384": ("n16384_trace.md",
+               _csrc("pbp_decode.hip", "pbp_generic_decoder.h")),
+    "sc": ("sc_decode_n1024_trace.md", _csrc("pbp_sc.hip")),
+    "quant": ("quant_decode_n1024_3db_trace.md", _csrc("pbp_quant.hip")),
+    "round_trip": ("round_trip_trace.md", _csrc("pbp_roundtrip.hip")),
+}
+COUNTER_RECORDS = {
+    "n1024": ("counters_bp_decode_r10_n1024_3db.md", KERNEL_SRCS),
+}
 
 MODES = {
     "es_frz": dict(early_stop=True, freezing=True, freeze_input=1, freeze_walk=0),
@@ -139,12 +158,10 @@ def source_digest(srcs=None):
     return h.hexdigest()[:16]
 
 
-def measured_traffic(workload="n1024", frames=None):
-    """HBM bytes per launch of a workload's roofline kernel from the
-    FETCH_SIZE and WRITE_SIZE counter runs recorded in its profile summary,
-    scaled by what the same counters read for a plain copy of known size;
-    None when the kernel source has changed since the counters were taken."""
-    name, srcs = TRAFFIC_RECORDS[workload]
+def _record(name, srcs, frames=None):
+    """The machine-read lines (``@key = value``) of a profile summary, or
+    None when it is missing, was taken on other kernel sources, or (frames
+    given) on another number of frames per launch."""
     vals = {}
     try:
         with open(os.path.join(ROOT, "profiles", name)) as f:
@@ -158,10 +175,46 @@ def measured_traffic(workload="n1024", frames=None):
         return None
     if frames is not None and vals.get("frames_per_launch") != str(frames):
         return None
+    return vals
+
+
+def _record_float(vals, key):
     try:
-        return float(vals["traffic_bytes_per_launch"])
+        return float(vals[key]) if vals is not None else None
     except (KeyError, ValueError):
         return None
+
+
+def measured_traffic(workload="n1024", frames=None):
+    """HBM bytes per launch of a workload's roofline kernel from the
+    FETCH_SIZE and WRITE_SIZE counter runs recorded in its profile summary,
+    scaled by what the same counters read for a plain copy of known size;
+    None when the kernel source has changed since the counters were taken."""
+    name, srcs = TRAFFIC_RECORDS[workload]
+    return _record_float(_record(name, srcs, frames),
+                         "traffic_bytes_per_launch")
+
+
+def traced_kernel_ms(workload, kernel, frames):
+    """The average duration (ms) of `kernel`'s dispatches in the workload's
+    committed kernel trace, or None (missing, stale or other frames)."""
+    name, srcs = TRACE_RECORDS[workload]
+    v = _record_float(_record(name, srcs, frames), f"avg_ns[{kernel}]")
+    return None if v is None else v / 1e6
+
+
+def valu_issue(workload, kernel, frames, ms):
+    """Fraction of the VALU lane rate the kernel's issued VALU instructions
+    fill: SQ_INSTS_VALU x 64 lanes over (lane peak x launch time), from the
+    committed counters run (None when missing or stale)."""
+    if workload not in COUNTER_RECORDS:
+        return None
+    name, srcs = COUNTER_RECORDS[workload]
+    n = _record_float(_record(name, srcs, frames),
+                      f"sq_insts_valu_per_launch[{kernel}]")
+    if n is None or not ms:
+        return None
+    return n * 64 / (VALU_PEAK_TOPS * 1e12 * ms / 1e3)
 
 
 def copy_calibration(torch, nbytes, reps):
@@ -185,44 +238,93 @@ def _oracle_frozen(N, K):
     return np.array(fz, dtype=np.uint8)
 
 
-def cpu_baseline(llr, K, info_ref, opts, seconds):
-    """The FP32 oracle on the host's cores over a bounded sample of the same
-    frames, in chunks, until the time budget is spent."""
+def host_cpu():
+    """(CPU model, logical CPUs this process may run on, threads an all-core
+    run uses: at most 16, the CPU share of one GPU on a shared host)."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for ln in f:
+                if ln.startswith("model name"):
+                    model = ln.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        avail = os.cpu_count() or 1
+    return model, avail, max(1, min(16, avail))
+
+
+def _oracle_timed(llr, frozen, opts, threads, seconds, chunk,
+                  decode=None):
+    """Decode chunks of llr (host) with the oracle on `threads` threads, in
+    order and wrapping round, until `seconds` have passed (every thread
+    finishes its chunk).  Returns (frames decoded, wall seconds, {first
+    frame of a chunk: oracle result} for the first pass)."""
     import threading
     from concurrent.futures import ThreadPoolExecutor
 
     import oracle
-    frozen = _oracle_frozen(llr.shape[1], K)
-    threads = max(1, min(16, os.cpu_count() or 1))
-    chunk = 16
+    if decode is None:
+        def decode(x):
+            return oracle.decode(x, frozen, **opts)
+    B = len(llr)
     nxt = [0]
     lock = threading.Lock()
-    done = []
+    first = {}
+    count = [0]
     t0 = time.perf_counter()
     deadline = t0 + seconds
 
     def worker():
         while time.perf_counter() < deadline:
             with lock:
-                lo = nxt[0]
-                if lo >= len(llr):
-                    return
-                nxt[0] += chunk
-            r = oracle.decode(llr[lo:lo + chunk], frozen, **opts)
-            done.append((lo, r["info"]))
-
+                k = nxt[0]
+                nxt[0] += 1
+            lo = (k * chunk) % B if B > chunk else 0
+            hi = min(B, lo + chunk)
+            r = decode(llr[lo:hi])
+            with lock:
+                count[0] += hi - lo
+                if k * chunk < B:
+                    first[lo] = r
     with ThreadPoolExecutor(threads) as ex:
         for f in [ex.submit(worker) for _ in range(threads)]:
             f.result()
-    wall = time.perf_counter() - t0
-    frames = sum(len(i) for _, i in done)
-    mism = sum(int(np.sum(np.any(i != info_ref[lo:lo + len(i)], axis=1)))
-               for lo, i in done)
-    return {"value": frames * K / wall / 1e6, "unit": "Mbit/s",
-            "cores": threads, "kind": "oracle",
-            "sample": f"{frames} frames of the timed batch, FP32 oracle, "
-                      f"{threads} threads, {wall:.1f} s",
-            "frames": frames, "gpu_mismatches": mism}
+    return count[0], time.perf_counter() - t0, first
+
+
+def cpu_baseline(llr, K, info_ref, opts, seconds, chunk=16, decode=None,
+                 key="info", what="FP32 oracle"):
+    """The oracle on the host over a bounded sample of the same frames,
+    single-threaded for half the time budget and on all the cores it may use
+    for the other half; each leg's first pass is checked against the GPU's
+    bits (`info_ref`, rows of the sample)."""
+    model, avail, threads = host_cpu()
+    frozen = _oracle_frozen(llr.shape[1], K)
+    legs = {}
+    mism = 0
+    for name, nt in (("single_thread", 1), ("all_cores", threads)):
+        n, wall, first = _oracle_timed(llr, frozen, opts, nt, seconds / 2,
+                                       chunk, decode)
+        mism += sum(int(np.sum(np.any(r[key] != info_ref[lo:lo + len(r[key])],
+                                      axis=1)))
+                    for lo, r in first.items())
+        legs[name] = {"value": round(n * K / wall / 1e6, 4),
+                      "frames_per_s": round(n / wall, 1), "threads": nt,
+                      "frames": n, "seconds": round(wall, 2)}
+    a = legs["all_cores"]
+    return {"value": a["value"], "unit": "Mbit/s", "cores": threads,
+            "kind": "oracle",
+            "sample": f"{what} over the first {len(llr)} frames of the "
+                      f"timed batch (wrapping round), {seconds / 2:g} s "
+                      f"single-threaded then {seconds / 2:g} s on {threads} "
+                      "threads",
+            "cpu_model": model, "host_cpus_visible": avail,
+            "single_thread": legs["single_thread"], "all_cores": a,
+            "gpu_mismatches": mism}
 
 
 def _oracle_all(llr, frozen, opts, threads, chunk=256):
@@ -298,7 +400,9 @@ def main():
                     help="frames per step (0: the workload's default)")
     ap.add_argument("--ebn0", type=float, default=None,
                     help="Eb/N0 in dB (default: the workload's)")
-    ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    ap.add_argument("--cpu-seconds", type=float, default=20.0,
+                    help="CPU baseline time budget, split between a "
+                         "single-threaded and an all-core run")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-reference-modes", action="store_true")
     ap.add_argument("--full-parity", action="store_true",
@@ -307,13 +411,16 @@ def main():
                          "counts compared) and with the FP64 oracle in the "
                          "headline mode (error-rate interval); takes minutes")
     ap.add_argument("--workload", default="n1024",
-                    choices=["n1024", "n16384", "mixed", "unrolled", "sweep",
-                             "round_trip"],
-                    help="n1024: the headline line (default); n16384: the "
+                    choices=["n1024", "c1", "n16384", "mixed", "unrolled",
+                             "sweep", "round_trip", "sc", "quant"],
+                    help="n1024: the headline line (default); c1: the "
+                         "(64,32) code with every frame checked; n16384: the "
                          "long-code decoder; mixed: the mixed-code persistent "
                          "decoder; unrolled: one training step of the "
-                         "unrolled decoder; round_trip: the round-trip "
-                         "schedule on the headline's frames")
+                         "unrolled decoder; sweep: every mode over Eb/N0; "
+                         "round_trip: the round-trip schedule on the "
+                         "headline's frames; sc: successive cancellation; "
+                         "quant: 8-bit fixed-point BP")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run a plain device copy of BYTES (counter "
                          "yardstick) and exit")
@@ -331,9 +438,10 @@ def main():
         copy_calibration(torch, args.copy_calibration, max(1, args.steps))
         return
     if args.workload != "n1024":
-        fn = {"n16384": bench_long_code, "mixed": bench_mixed,
-              "unrolled": bench_unrolled, "sweep": bench_sweep,
-              "round_trip": bench_round_trip}[args.workload]
+        fn = {"c1": bench_c1, "n16384": bench_long_code,
+              "mixed": bench_mixed, "unrolled": bench_unrolled,
+              "sweep": bench_sweep, "round_trip": bench_round_trip,
+              "sc": bench_sc, "quant": bench_quant}[args.workload]
         print(json.dumps(fn(args, pbp, torch)), flush=True)
         return
 
@@ -391,12 +499,8 @@ def main():
     }
     pe_total = h["pe"] * B
     achieved = OPS_PER_PE * pe_total / (h["ms"] / 1e3) / 1e12
-    line["roofline"] = {"bound": "alu", "achieved": round(achieved, 3),
-                        "peak": round(VALU_PEAK_TOPS, 3), "unit": "TOP/s",
-                        "frac": round(achieved / VALU_PEAK_TOPS, 4),
-                        "traffic": measured_traffic("n1024", B),
-                        "kernel": KERNEL,
-                        "kernel_ms": round(h["ms"], 4)}
+    line["roofline"] = _alu_roofline(achieved, "n1024", KERNEL, B, h["ms"],
+                                     "12 operations per PE activation")
     if "plain" in res:
         p, e = res["plain"], res["es"]
         lo_f, _ = wilson(h["errors"], B, 1.6448536269514722)
@@ -420,6 +524,33 @@ def main():
                                                               res, K)
     line["input_generation_s"] = round(gen_s, 2)
     print(json.dumps(line), flush=True)
+
+
+def _alu_roofline(achieved, workload, kernel, frames, event_ms, note):
+    """The roofline object of a VALU-bound kernel: `achieved` algorithmic
+    TOP/s over the launch time measured live (`event_ms`, HIP events on the
+    launch stream); `kernel_ms` is the average dispatch duration in the
+    workload's committed kernel trace (None when stale), and
+    `valu_issue_frac` the issued VALU instructions' share of the lane rate
+    from the committed counters run, where one exists."""
+    tr = TRACE_RECORDS.get(workload)
+    r = {"bound": "alu", "achieved": round(achieved, 4),
+         "peak": round(VALU_PEAK_TOPS, 3), "unit": "TOP/s",
+         "frac": round(achieved / VALU_PEAK_TOPS, 5),
+         "traffic": (measured_traffic(workload, frames)
+                     if workload in TRAFFIC_RECORDS else None),
+         "kernel": kernel,
+         "kernel_ms": (None if tr is None else
+                       _round(traced_kernel_ms(workload, kernel, frames), 4)),
+         "event_ms": round(event_ms, 4),
+         "valu_issue_frac": _round(valu_issue(workload, kernel, frames,
+                                              event_ms), 4),
+         "note": note}
+    return r
+
+
+def _round(v, nd):
+    return None if v is None else round(v, nd)
 
 
 # ---------------------------------------------------------------------------
@@ -511,10 +642,205 @@ def bench_long_code(args, pbp, torch):
                   "frac": round(gbs / HBM_PEAK_GBS, 4),
                   "traffic": measured_traffic("n16384", B),
                   "kernel": "bp_decode_kernel<14, true>",
-                  "kernel_ms": round(ms, 4)},
+                  "kernel_ms": _round(traced_kernel_ms(
+                      "n16384", "bp_decode_kernel<14, true>", B), 4),
+                  "event_ms": round(ms, 4)},
         valu={"achieved": round(ops, 3), "peak": round(VALU_PEAK_TOPS, 3),
               "unit": "TOP/s", "frac": round(ops / VALU_PEAK_TOPS, 4)},
         **extra)
+
+
+def bench_c1(args, pbp, torch):
+    """The (64, 32) code (design Eb/N0 0 dB) at Eb/N0 2.5 dB, early stop, at
+    most 40 iterations, 10^4 frames.  Every frame is checked against the
+    FP32 oracle (bits, iterations, PE counts), and the error rate against the
+    FP64 oracle's 95% interval."""
+    N, K, max_iter, alpha = 64, 32, 40, 0.9375
+    ebn0 = 2.5 if args.ebn0 is None else args.ebn0
+    B = args.batch or 10 ** 4
+    frozen = pbp.pbp_construct(N, K, 0.0)
+    code = pbp.Code(N, K, frozen)
+    info, d_llr = make_inputs(pbp, torch, code, frozen, N, K, B, ebn0,
+                              stream=(1 << 16) + 1)
+    opts = dict(MODES["es"], max_iter=max_iter, alpha=alpha)
+    # a launch decodes 10^4 short frames in tens of microseconds: more steps
+    steps = args.steps * 10
+    ms, _, out, med, e2e = time_mode(pbp, torch, code, d_llr, opts, steps,
+                                     args.warmup)
+    errs = int(np.sum(np.any(out["info"] != info, axis=1)))
+    pe = out["pe"].astype(np.float64)
+    llr = d_llr.cpu().numpy()
+    fz = _oracle_frozen(N, K)
+    _, _, threads = host_cpu()
+    print(f"[parity] C1: FP32 and FP64 oracle on {B} frames", file=sys.stderr,
+          flush=True)
+    o = _oracle_all(llr, fz, opts, threads)
+    o64 = _oracle_all(llr, fz, dict(opts, prec="f64"), threads)
+    e64 = int(np.sum(np.any(o64["info"] != info, axis=1)))
+    lo, hi = wilson(e64, B, 1.959963984540054)
+    parity = {"frames": B,
+              "fp32_mismatched_frames": _compare(o, out["info"], out["iters"],
+                                                 out["pe"]),
+              "fp64_fer": e64 / B, "fp64_fer_ci95": [lo, hi],
+              "gpu_inside_fp64_ci95": bool(lo <= errs / B <= hi)}
+    achieved = OPS_PER_PE * pe.sum() / (ms / 1e3) / 1e12
+    line = _line(
+        "decoded info Mbit/s, N=64 R=1/2 2.5dB, early stop",
+        round(B * K / ms / 1e3, 3), "Mbit/s", steps, args.warmup, ms,
+        {"workload": "polar BP decode, (64,32) code, BPSK/AWGN Eb/N0 "
+                     f"{ebn0} dB, G-matrix early stop, no freezing",
+         "N": N, "K": K, "ebn0_db": ebn0, "frames_per_step": B,
+         "max_iter": max_iter, "alpha": alpha},
+        avg_iters=round(float(out["iters"].mean()), 3),
+        pe_per_frame=round(float(pe.mean()), 1), fer=errs / B,
+        ms_per_step_median=round(med, 4), end_to_end_ms=round(e2e, 3),
+        parity=parity,
+        roofline=_alu_roofline(achieved, "c1", "bp_decode_kernel<6, false>",
+                               B, ms, "12 operations per PE activation"))
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(llr, K, out["info"], opts,
+                                            args.cpu_seconds, chunk=256)
+    return line
+
+
+# Operations of one SC frame: m N / 2 evaluations of f (magnitude minimum,
+# sign product) and m N / 2 of g (sign flip by the partial sum, addition)
+def sc_ops_per_frame(N):
+    return 2 * (N.bit_length() - 1) * N
+
+
+def bench_sc(args, pbp, torch):
+    """Successive-cancellation decoding of the (1024, 512) code on the
+    headline's frames (3.0 dB, 10^6 frames): decode rate, error rate beside
+    BP with early stop and freezing on the same frames, and the decisions
+    against the SC oracle frame by frame (a sample of 2^16 frames, or every
+    frame with --full-parity)."""
+    import oracle
+    N, K = 1024, 512
+    ebn0 = 3.0 if args.ebn0 is None else args.ebn0
+    B = args.batch or 10 ** 6
+    frozen = pbp.pbp_construct(N, K, 0.0)
+    code = pbp.Code(N, K, frozen)
+    info, d_llr = make_inputs(pbp, torch, code, frozen, N, K, B, ebn0,
+                              stream=(2 << 16) + 5)
+    out = pbp.pbp_decode_sc(code, d_llr)
+    ms = _timed(torch, lambda: pbp.pbp_decode_sc(code, d_llr, out=out),
+                args.steps, args.warmup)
+    got = out["info"].cpu().numpy()
+    errs = int(np.sum(np.any(got != info, axis=1)))
+    bp = pbp.pbp_decode(code, d_llr, max_iter=40, alpha=0.9375,
+                        **MODES["es_frz"])
+    bp_errs = int(np.sum(np.any(bp["info"].cpu().numpy() != info, axis=1)))
+    z = 1.959963984540054
+    fz = _oracle_frozen(N, K)
+
+    def sc_oracle(x):
+        return {"info": oracle.sc_decode(x, fz)[:, fz == 0]}
+
+    S = B if args.full_parity else min(B, 1 << 16)
+    _, _, threads = host_cpu()
+    print(f"[parity] SC oracle on {S} frames", file=sys.stderr, flush=True)
+    llr_s = d_llr[:S].cpu().numpy()
+    parts = {}
+    from concurrent.futures import ThreadPoolExecutor
+
+    def job(lo):
+        parts[lo] = sc_oracle(llr_s[lo:lo + 1024])["info"]
+    with ThreadPoolExecutor(threads) as ex:
+        list(ex.map(job, range(0, S, 1024)))
+    ref = np.concatenate([parts[k] for k in sorted(parts)])
+    mism = int(np.sum(np.any(ref != got[:S], axis=1)))
+    achieved = sc_ops_per_frame(N) * B / (ms / 1e3) / 1e12
+    line = _line(
+        "decoded info Mbit/s, N=1024 R=1/2 3.0dB, successive cancellation",
+        round(B * K / ms / 1e3, 2), "Mbit/s", args.steps, args.warmup, ms,
+        {"workload": "polar SC decode, (1024,512) code, BPSK/AWGN Eb/N0 "
+                     f"{ebn0} dB, the headline's frames",
+         "N": N, "K": K, "ebn0_db": ebn0, "frames_per_step": B},
+        fer=errs / B, fer_ci95=list(wilson(errs, B, z)),
+        bp_es_freeze_fer=bp_errs / B,
+        bp_es_freeze_fer_ci95=list(wilson(bp_errs, B, z)),
+        parity={"frames": S, "mismatched_frames": mism},
+        roofline=_alu_roofline(
+            achieved, "sc", "sc_decode_kernel<10>", B, ms,
+            "2 m N operations per frame (m N / 2 f and m N / 2 g "
+            "evaluations); one wavefront walks a frame's leaves in order"))
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(
+            llr_s[:1 << 16], K, got, {}, args.cpu_seconds, chunk=64,
+            decode=sc_oracle, what="FP32 SC oracle")
+    return line
+
+
+def bench_quant(args, pbp, torch):
+    """BP with saturating 8-bit fixed-point messages (3 fraction bits) on the
+    headline's frames and mode (3.0 dB, 10^6 frames, early stop + freezing):
+    decode rate, error rate beside FP32 BP on the same frames, and bits,
+    iterations and PE counts against the fixed-point oracle frame by frame
+    (a sample of 2^15 frames, or every frame with --full-parity)."""
+    import oracle
+    N, K, max_iter, alpha, bits, frac = 1024, 512, 40, 0.9375, 8, 3
+    ebn0 = 3.0 if args.ebn0 is None else args.ebn0
+    B = args.batch or 10 ** 6
+    frozen = pbp.pbp_construct(N, K, 0.0)
+    code = pbp.Code(N, K, frozen)
+    info, d_llr = make_inputs(pbp, torch, code, frozen, N, K, B, ebn0,
+                              stream=(2 << 16) + 5)
+    opts = dict(MODES["es_frz"], max_iter=max_iter, alpha=alpha)
+    out = pbp.pbp_decode_quant(code, d_llr, bits=bits, frac=frac, **opts)
+    ms = _timed(torch, lambda: pbp.pbp_decode_quant(
+        code, d_llr, bits=bits, frac=frac, out=out, **opts),
+        args.steps, args.warmup)
+    got = {k: v.cpu().numpy() for k, v in out.items()}
+    errs = int(np.sum(np.any(got["info"] != info, axis=1)))
+    bp = pbp.pbp_decode(code, d_llr, **opts)
+    bp_errs = int(np.sum(np.any(bp["info"].cpu().numpy() != info, axis=1)))
+    z = 1.959963984540054
+    fz = _oracle_frozen(N, K)
+
+    def q_oracle(x):
+        return oracle.decode_quant(x, fz, bits=bits, frac=frac, **opts)
+
+    S = B if args.full_parity else min(B, 1 << 15)
+    _, _, threads = host_cpu()
+    print(f"[parity] fixed-point oracle on {S} frames", file=sys.stderr,
+          flush=True)
+    llr_s = d_llr[:S].cpu().numpy()
+    parts = {}
+    from concurrent.futures import ThreadPoolExecutor
+
+    def job(lo):
+        parts[lo] = q_oracle(llr_s[lo:lo + 256])
+    with ThreadPoolExecutor(threads) as ex:
+        list(ex.map(job, range(0, S, 256)))
+    o = {k: np.concatenate([parts[lo][k] for lo in sorted(parts)])
+         for k in ("info", "iters", "pe")}
+    mism = _compare(o, got["info"][:S], got["iters"][:S], got["pe"][:S])
+    pe = got["pe"].astype(np.float64)
+    achieved = OPS_PER_PE * pe.sum() / (ms / 1e3) / 1e12
+    line = _line(
+        "decoded info Mbit/s, N=1024 R=1/2 3.0dB, 8-bit fixed-point BP",
+        round(B * K / ms / 1e3, 2), "Mbit/s", args.steps, args.warmup, ms,
+        {"workload": "polar BP decode with saturating 8-bit messages (3 "
+                     "fraction bits), (1024,512) code, BPSK/AWGN Eb/N0 "
+                     f"{ebn0} dB, early stop + CSFG freezing, the headline's "
+                     "frames",
+         "N": N, "K": K, "ebn0_db": ebn0, "frames_per_step": B,
+         "max_iter": max_iter, "alpha": alpha, "bits": bits, "frac": frac},
+        avg_iters=round(float(got["iters"].mean()), 3),
+        pe_per_frame=round(float(pe.mean()), 1),
+        fer=errs / B, fer_ci95=list(wilson(errs, B, z)),
+        fp32_fer=bp_errs / B, fp32_fer_ci95=list(wilson(bp_errs, B, z)),
+        parity={"frames": S, "mismatched_frames": mism},
+        roofline=_alu_roofline(achieved, "quant", "quant_decode_kernel<10>",
+                               B, ms, "12 integer operations per PE "
+                               "activation"))
+    line["dtype"] = "i8"
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(
+            llr_s, K, got["info"], {}, args.cpu_seconds, chunk=16,
+            decode=q_oracle, what="fixed-point oracle")
+    return line
 
 
 def bench_mixed(args, pbp, torch):
@@ -680,9 +1006,10 @@ def bench_mixed(args, pbp, torch):
         **extra)
 
 
-# FP32 operations per PE activation of one round-trip pass: each pass
-# computes two outputs of eq. (1), each an add, a median and a scaling
-OPS_PER_PE_PASS = 6
+# Operations per PE activation of one round-trip pass, counted as for the
+# single sweep: each pass computes two outputs of eq. (1), each a min-sum
+# term (sign product, magnitude minimum, scaling) and an addition
+OPS_PER_PE_PASS = 8
 
 
 def bench_round_trip(args, pbp, torch):
@@ -728,13 +1055,10 @@ def bench_round_trip(args, pbp, torch):
             "fer_ci95": list(wilson(s1["errors"], B, 1.959963984540054)),
             "avg_iters": round(s1["iters"], 3),
             "pe_per_frame": round(s1["pe"], 1)},
-        roofline={"bound": "alu", "achieved": round(achieved, 3),
-                  "peak": round(VALU_PEAK_TOPS, 3), "unit": "TOP/s",
-                  "frac": round(achieved / VALU_PEAK_TOPS, 4),
-                  "traffic": None, "kernel": "bp_round_trip_kernel<10>",
-                  "kernel_ms": round(r["ms"], 4),
-                  "note": "6 FP32 operations per PE activation of one pass, "
-                          "m N activations per iteration"})
+        roofline=_alu_roofline(achieved, "round_trip",
+                               "bp_round_trip_kernel<10>", B, r["ms"],
+                               "8 operations per PE activation of one pass, "
+                               "m N activations per iteration"))
     if not args.no_cpu_baseline:
         d_host = d_llr[:min(B, 1 << 19)].cpu().numpy()
         line["cpu_baseline"] = cpu_baseline(
@@ -917,6 +1241,13 @@ def bench_sweep(args, pbp, torch):
                 row[name]["oracle_mismatched_frames"] = _compare(
                     o, out["info"][:S].cpu().numpy(),
                     out["iters"][:S].cpu().numpy(), out["pe"][:S].cpu().numpy())
+        # successive cancellation on the same LLRs
+        sc = pbp.pbp_decode_sc(code, d_llr)
+        ms = _timed(torch, lambda: pbp.pbp_decode_sc(code, d_llr, out=sc), 1, 0)
+        errs = int(np.sum(np.any(sc["info"].cpu().numpy() != info, axis=1)))
+        lo, hi = wilson(errs, B, 1.959963984540054)
+        row["sc"] = {"fer": errs / B, "fer_ci95": [lo, hi],
+                     "mbps": round(B * K / ms / 1e3, 1)}
         table.append(row)
         del d_llr
         print(f"[sweep] {eb} dB done", file=sys.stderr, flush=True)
@@ -931,8 +1262,8 @@ def bench_sweep(args, pbp, torch):
         "all decoding modes", round(fz["mbps"], 2), "Mbit/s (3.0 dB, early "
         "stop + freezing)", 1, 0, total_ms,
         {"workload": "(1024,512) code, Eb/N0 1.0-3.5 dB, "
-                     f"{B} frames per point, {len(SWEEP_MODES)} modes on "
-                     "the same LLRs",
+                     f"{B} frames per point, {len(SWEEP_MODES)} BP modes "
+                     "and SC decoding on the same LLRs",
          "frames_per_point": B, "max_iter": max_iter, "alpha": alpha},
         reductions_at_3db=ctx,
         paper_reductions_at_3db={"iterations_vs_plain40": 0.46,

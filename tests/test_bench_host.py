@@ -24,9 +24,37 @@ def test_more_than_one_gpu_is_refused_with_a_message():
 def test_fp32_lane_peak_from_unit_counts():
     # 256 compute units x 4 SIMDs x 16 lanes x 2.4 GHz, in T op/s
     assert bench.VALU_PEAK_TOPS == pytest.approx(39.3216)
-    # eq. (1): 3 adds, 3 medians, 3 scalings per PE (sign products are
-    # bitwise and not counted against the FP32 lanes)
-    assert bench.OPS_PER_PE == 9
+    # eq. (1): three distinct min-sum terms (sign product, magnitude
+    # minimum, scaling) and three additions per PE
+    assert bench.OPS_PER_PE == 12
+    # one round-trip pass computes two outputs: two terms and two additions
+    assert bench.OPS_PER_PE_PASS == 8
+    # SC: m N / 2 evaluations each of f and g, two operations each
+    assert bench.sc_ops_per_frame(1024) == 20480
+
+
+def test_record_readers(tmp_path, monkeypatch):
+    """Trace and counter records give the kernel time and the VALU issue
+    fraction only while their sources and frame count match."""
+    src = tmp_path / "k.hip"
+    src.write_text("kernel")
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    (tmp_path / "profiles").mkdir()
+    rec = tmp_path / "profiles" / "t.md"
+    monkeypatch.setitem(bench.TRACE_RECORDS, "t", ("t.md", [str(src)]))
+    monkeypatch.setitem(bench.COUNTER_RECORDS, "t", ("t.md", [str(src)]))
+    digest = bench.source_digest([str(src)])
+    rec.write_text(f"@source_sha256_16 = {digest}\n@frames_per_launch = 100\n"
+                   "@avg_ns[k<1>] = 2500000\n"
+                   "@sq_insts_valu_per_launch[k<1>] = 1228800000\n")
+    assert bench.traced_kernel_ms("t", "k<1>", 100) == pytest.approx(2.5)
+    assert bench.traced_kernel_ms("t", "k<1>", 99) is None
+    assert bench.traced_kernel_ms("t", "k<2>", 100) is None
+    # 1.2288e9 instructions x 64 lanes in 2.5 ms over 39.3216e12 lane-op/s
+    assert bench.valu_issue("t", "k<1>", 100, 2.5) == pytest.approx(0.8)
+    src.write_text("changed kernel")
+    assert bench.traced_kernel_ms("t", "k<1>", 100) is None
+    assert bench.valu_issue("t", "k<1>", 100, 2.5) is None
 
 
 def test_every_traffic_record_names_existing_sources():
