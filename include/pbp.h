@@ -127,11 +127,15 @@ int32_t pbp_encode(const pbp_code *code, const uint8_t *info, int64_t B,
  *             computation count), or NULL
  *   soft_out  device, B x N FP32, or NULL: the posterior LLR of each source
  *             bit at exit (R + L at column m+1; +-inf inside frozen CSFGs)
- * The frame counter of the persistent kernels and the message state of codes
- * longer than 1024 come from the stream's workspace (see the conventions
- * above), so calls on different streams may overlap, on one handle or
- * several.  The message state takes (m + 1) N floats per resident
- * workgroup: 503 MB on 256 compute units at N = 16384.
+ * Codes up to N = 4096 keep every message on chip (N = 1024: one wavefront
+ * per frame, registers and LDS; N = 2048, 4096: one workgroup of N/4
+ * threads per frame, half the L columns in VGPRs, the rest in LDS).  Longer
+ * codes keep L in device memory.  The frame counter of the persistent
+ * kernels and the message state of codes longer than 4096 come from the
+ * stream's workspace (see the conventions above), so calls on different
+ * streams may overlap, on one handle or several.  The message state takes
+ * (m + 1) N floats per resident workgroup: 503 MB on 256 compute units at
+ * N = 16384.
  * Errors: PBP_EINVAL (bad options, B < 0, NULL required pointer; checked
  * before any allocation), PBP_ENOMEM (the workspace cannot be allocated),
  * PBP_EDEVICE (launch failure). */
@@ -150,12 +154,12 @@ int32_t pbp_workspace_release(void *stream);
 /* pbp_decode for callers that cannot allocate device memory (code under
  * graph capture, tight serving loops, harnesses that forbid hipMalloc):
  * the same decoding, arguments and results bit for bit, with the scratch of
- * the persistent kernels (the N = 1024 kernel's frame counter, the message
- * state of codes longer than 1024) taken from a static 64 MiB device array
- * instead of the stream's workspace, and no allocation of any kind.  Each
- * GPU holds one such array until the process ends; codes longer than 1024
- * run at most as many resident workgroups as state slots fit in it (683 at
- * N = 2048, 315 at N = 4096, 68 at N = 16384).  Every call on a GPU shares
+ * the persistent kernels (the frame counter of the N = 1024, 2048 and 4096
+ * kernels, the message state of longer codes) taken from a static 64 MiB
+ * device array instead of the stream's workspace, and no allocation of any
+ * kind.  Each GPU holds one such array until the process ends; codes longer
+ * than 4096 run at most as many resident workgroups as state slots fit in
+ * it (146 at N = 8192, 68 at N = 16384).  Every call on a GPU shares
  * that array, so calls that overlap on one GPU (two streams, or two
  * threads) race; order them on one stream.  B must be at most 2^30.
  * Errors: as pbp_decode; PBP_EINVAL also for B > 2^30, PBP_EDEVICE when the

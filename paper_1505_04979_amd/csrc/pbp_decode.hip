@@ -2,14 +2,17 @@
 //
 // Batch decoder: one workgroup decodes one frame at a time (grid-stride over
 // the batch) with the generic decoder of pbp_generic_decoder.h, its message
-// state in LDS (N <= 1024) or in a per-workgroup slot of device memory
-// (larger N).  N = 1024 goes to the register-resident decoder instead.
+// state in LDS (N <= 512) or in a per-workgroup slot of device memory
+// (N >= 8192).  N = 1024 goes to the register-resident decoder and N = 2048
+// and 4096 to the workgroup-resident decoder (pbp_pair_decoder.h), both
+// taking frames from the stream's counter.
 #include <hip/hip_runtime.h>
 
 #include <mutex>
 
 #include "pbp_generic_decoder.h"
 #include "pbp_internal.h"
+#include "pbp_pair_decoder.h"
 #include "pbp_r10.h"
 
 namespace {
@@ -28,6 +31,39 @@ __global__ __launch_bounds__(256, M >= 14 ? 2 : 4) void bp_decode_kernel(DecodeP
         decode_frame<M, GSTATE ? 1 : 0, false>(P, frame, smem, gslot,
                                                (int)threadIdx.x,
                                                (int)blockDim.x);
+}
+
+// N = 2048 and 4096: one workgroup of N / 4 threads per frame, messages on
+// chip; frames come from the counter pair (next frame, groups out), which
+// the last group out rewinds, or by grid stride when there is none.
+template <int M>
+__global__ __launch_bounds__(pbp::pair::Shape<M>::NT) void bp_decode_pair_kernel(
+    DecodeParams P, int *counter)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ int s_frame;
+    const int tid = (int)threadIdx.x;
+    pbp::pair::Decoder<M> D(P, smem, tid);
+    int64_t frame = blockIdx.x;
+    for (;;) {
+        if (counter) {
+            if (tid == 0)
+                s_frame = atomicAdd(counter, 1);
+            __syncthreads();
+            frame = s_frame;
+            __syncthreads();
+        }
+        if (frame >= P.B)
+            break;
+        D.decode(frame);
+        if (!counter)
+            frame += gridDim.x;
+    }
+    if (counter && tid == 0 &&
+        atomicAdd(counter + 1, 1) == (int)gridDim.x - 1) {
+        atomicExch(counter, 0);
+        atomicExch(counter + 1, 0);
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -63,7 +99,7 @@ size_t decode_lds_bytes(bool gstate)
     return lds_bytes<M>(gstate ? 1 : 0);
 }
 
-// state, slots: the message state of codes longer than 1024 (one slot of
+// state, slots: the message state of codes longer than 4096 (one slot of
 // (m + 1) N floats per resident workgroup, so at most `slots` groups)
 template <int M>
 hipError_t launch_decode(const pbp_code *c, DecodeParams &P, float *state,
@@ -92,6 +128,36 @@ hipError_t launch_decode(const pbp_code *c, DecodeParams &P, float *state,
     return hipGetLastError();
 }
 
+// counter: the frame counter pair (zero), or null for a grid-stride launch
+template <int M>
+hipError_t launch_pair(const pbp_code *c, DecodeParams &P, int *counter,
+                       hipStream_t st)
+{
+    using S = pbp::pair::Shape<M>;
+    const size_t lds = pbp::pair::lds_bytes<M>();
+    auto kern = bp_decode_pair_kernel<M>;
+    hipError_t e = hipFuncSetAttribute((const void *)kern,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)lds);
+    if (e != hipSuccess)
+        return e;
+    // resident groups per compute unit (once per process: LDS bound)
+    static int occ = 0;
+    if (occ < 1) {
+        int o = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&o, (const void *)kern,
+                                                         S::NT, lds) != hipSuccess)
+            return hipGetLastError();
+        occ = o < 1 ? 1 : o;
+    }
+    int64_t grid = (int64_t)c->cus * occ;
+    if (grid > P.B)
+        grid = P.B;
+    int *ctr = P.B <= (int64_t(1) << 30) ? counter : nullptr;
+    hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(S::NT), lds, st, P, ctr);
+    return hipGetLastError();
+}
+
 }  // namespace
 
 extern "C" int32_t pbp_encode(const pbp_code *code, const uint8_t *info,
@@ -113,7 +179,8 @@ extern "C" int32_t pbp_encode(const pbp_code *code, const uint8_t *info,
 namespace {
 
 // Device scratch of one decode call: the [frame, exit] counter pair of the
-// N = 1024 kernel and the message-state slots of codes longer than 1024.
+// N = 1024, 2048 and 4096 kernels and the message-state slots of codes
+// longer than 4096.
 struct Scratch {
     int *counter;
     float *state;
@@ -177,8 +244,8 @@ int32_t decode_impl(const pbp_code *code, const float *llr, int64_t B,
     case 8: e = launch_decode<8>(code, P, sc->state, sc->slots, st); break;
     case 9: e = launch_decode<9>(code, P, sc->state, sc->slots, st); break;
     case 10: e = launch_decode<10>(code, P, sc->state, sc->slots, st); break;
-    case 11: e = launch_decode<11>(code, P, sc->state, sc->slots, st); break;
-    case 12: e = launch_decode<12>(code, P, sc->state, sc->slots, st); break;
+    case 11: e = launch_pair<11>(code, P, sc->counter, st); break;
+    case 12: e = launch_pair<12>(code, P, sc->counter, st); break;
     case 13: e = launch_decode<13>(code, P, sc->state, sc->slots, st); break;
     case 14: e = launch_decode<14>(code, P, sc->state, sc->slots, st); break;
     default: return PBP_EUNSUPPORTED;
@@ -213,7 +280,7 @@ extern "C" int32_t pbp_decode(const pbp_code *code, const float *llr, int64_t B,
 //
 // The scratch of these calls is one static device array per GPU, so a call
 // needs no allocation: its first 256 bytes hold the counter pair, the rest
-// the message-state slots of codes longer than 1024.
+// the message-state slots of codes longer than 4096.
 namespace {
 
 constexpr size_t kScratchBytes = size_t(64) << 20;
@@ -252,10 +319,10 @@ __global__ void clear_counters_kernel(int *counter)
         counter[threadIdx.x] = 0;
 }
 
-// message-state slots that fit the scratch (codes longer than 1024)
+// message-state slots that fit the scratch (codes longer than 4096)
 int64_t scratch_slots(const pbp_code *code)
 {
-    if (code->m <= pbp::kMaxLdsLog)
+    if (code->m <= pbp::kMaxOnChipLog)
         return INT64_MAX;
     const int64_t slot = (int64_t)sizeof(float) * code->state_floats_per_slot;
     return (int64_t)((kScratchBytes - kScratchHead) / slot);
@@ -283,9 +350,11 @@ extern "C" int32_t pbp_decode_noalloc(const pbp_code *code, const float *llr,
     sc.state = reinterpret_cast<float *>(static_cast<unsigned char *>(base) +
                                          kScratchHead);
     sc.slots = scratch_slots(code);
-    if (code->m > pbp::kMaxLdsLog && sc.slots < 1)
+    if (code->m > pbp::kMaxOnChipLog && sc.slots < 1)
         return PBP_EUNSUPPORTED;
-    if (B > 0 && code->m == pbp::r10::M) {
+    // the persistent kernels (N = 1024, 2048, 4096) take frames from the
+    // counter pair
+    if (B > 0 && code->m >= pbp::r10::M && code->m <= pbp::kMaxOnChipLog) {
         hipLaunchKernelGGL(clear_counters_kernel, dim3(1), dim3(64), 0,
                            (hipStream_t)stream, sc.counter);
         if (hipGetLastError() != hipSuccess)

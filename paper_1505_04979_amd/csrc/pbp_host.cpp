@@ -162,8 +162,8 @@ extern "C" int32_t pbp_code_create(int32_t N, int32_t K, const uint8_t *frozen,
             return PBP_EDEVICE;
         }
     }
-    if (c->m > pbp::kMaxLdsLog) {
-        // message state of codes too long for LDS: one slot per resident
+    if (c->m > pbp::kMaxOnChipLog) {
+        // message state of codes too long for the chip: one slot per resident
         // workgroup, (m + 1) columns of N floats each, in the workspace of
         // the decoding stream.  The workgroups hold the working R column and
         // two bit words per 64 rows in LDS, so as many as fit in 160 KB (at

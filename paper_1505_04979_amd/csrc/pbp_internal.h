@@ -38,8 +38,11 @@ inline int log2i(int32_t N)
     return m;
 }
 
-// Largest code length whose full message state lives in LDS.
+// Largest code length whose full message state lives in LDS (the generic
+// and register decoders), and largest whose messages stay on chip (the
+// workgroup decoder of N = 2048 and 4096 keeps half its L columns in VGPRs).
 constexpr int kMaxLdsLog = 10;
+constexpr int kMaxOnChipLog = 12;
 
 // Device scratch of the decoders on one (device, stream): the [frame, exit]
 // counters of the persistent kernels (zero between launches) and the

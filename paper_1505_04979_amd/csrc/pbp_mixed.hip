@@ -13,8 +13,9 @@
 // order 1 -- frames grouped by code, longest code first.  A device counting
 //   sort builds the queue (an order array of frame indices, one contiguous
 //   segment per code); each code's segment is then drained by a kernel
-//   specialised for its length, N >= 2048 by 256-thread workgroups that
-//   share one slot per frame.
+//   specialised for its length: N = 2048 and 4096 by workgroups of N / 4
+//   threads with every message on chip (pbp_pair_decoder.h), longer codes
+//   by 256-thread workgroups that share one slot per frame.
 //
 // The last wavefront out of a launch rewinds its counters, so the enqueued
 // work needs no host-side or memset reset and can be captured in a graph and
@@ -34,6 +35,7 @@
 #include "pbp.h"
 #include "pbp_generic_decoder.h"
 #include "pbp_internal.h"
+#include "pbp_pair_decoder.h"
 #include "pbp_r10.h"
 #include "pbp_r10_decoder.h"
 
@@ -193,6 +195,59 @@ __global__ __launch_bounds__(kWgThreads, M >= 14 ? 2 : 4) void class_wg_kernel(C
         D.pe_out = P.pe_out ? P.pe_out + f : nullptr;
         D.soft_out = nullptr;
         decode_frame<M, 1, false>(D, 0, smem, gslot, tid, kWgThreads);
+        busy += wall_clock64() - t0;
+    }
+    if (tid == 0) {
+        P.stats[wg * 3] = t_start;
+        P.stats[wg * 3 + 1] = wall_clock64();
+        P.stats[wg * 3 + 2] = busy;
+        if (atomicAdd(P.counter + 1, 1) == (int)gridDim.x - 1) {
+            atomicExch(P.counter, 0);
+            atomicExch(P.counter + 1, 0);
+        }
+    }
+}
+
+// N = 2048 and 4096: the workgroup-resident decoder, N / 4 threads per
+// frame, every message on chip.
+template <int M>
+__global__ __launch_bounds__(pbp::pair::Shape<M>::NT) void class_pair_kernel(ClassParams P)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ int s_q;
+    const int tid = (int)threadIdx.x;
+    const int64_t wg = blockIdx.x;
+    const int lo = P.bounds[P.bucket], hi = P.bounds[P.bucket + 1];
+    const int64_t t_start = wall_clock64();
+    int64_t busy = 0;
+    for (;;) {
+        if (tid == 0)
+            s_q = atomicAdd(P.counter, 1) + lo;
+        __syncthreads();
+        const int q = s_q;
+        __syncthreads();
+        if (q >= hi)
+            break;
+        const int64_t t0 = wall_clock64();
+        const int f = P.order[q];
+        DecodeParams D{};
+        D.llr = P.llr + P.llr_off[f];
+        D.B = 1;
+        D.frozen_words = P.code.frozen_words;
+        D.info_pos = P.code.info_pos;
+        D.K = P.code.K;
+        D.max_iter = P.max_iter;
+        D.early_stop = P.early_stop;
+        D.freezing = P.freezing;
+        D.freeze_input = P.freeze_input;
+        D.freeze_walk = P.freeze_walk;
+        D.alpha = P.alpha;
+        D.info_out = P.info_out + P.info_off[f];
+        D.iters_out = P.iters_out + f;
+        D.pe_out = P.pe_out ? P.pe_out + f : nullptr;
+        D.soft_out = nullptr;
+        pbp::pair::Decoder<M> dec(D, smem, tid);
+        dec.decode(0);
         busy += wall_clock64() - t0;
     }
     if (tid == 0) {
@@ -504,7 +559,10 @@ struct Launch {
 template <int M, int PATH>
 Launch launch_of()
 {
-    if constexpr (PATH == 1) {
+    if constexpr (PATH == 2) {
+        return Launch{(const void *)class_pair_kernel<M>,
+                      pbp::pair::lds_bytes<M>(), pbp::pair::Shape<M>::NT};
+    } else if constexpr (PATH == 1) {
         return Launch{(const void *)class_wg_kernel<M>,
                       pbp::generic::lds_bytes<M>(1), kWgThreads};
     } else {
@@ -527,8 +585,8 @@ Launch class_launch(int m, int early_stop)
     case 8: return launch_of<8, 0>();
     case 9: return launch_of<9, 0>();
     case 10: return early_stop ? launch_of<10, 10>() : launch_of<10, 11>();
-    case 11: return launch_of<11, 1>();
-    case 12: return launch_of<12, 1>();
+    case 11: return launch_of<11, 2>();
+    case 12: return launch_of<12, 2>();
     case 13: return launch_of<13, 1>();
     case 14: return launch_of<14, 1>();
     default: return Launch{nullptr, 0};
@@ -754,9 +812,10 @@ extern "C" int32_t pbp_mixed_plan_create(const pbp_code *const *codes,
     }
     const int64_t waves = (int64_t)p->cus * kMaxWavesPerCu;
     int32_t st = PBP_OK;
-    // codes longer than 1024 keep L in a slot per resident workgroup: one
-    // per wavefront of the single kernel (order 0), which covers the
-    // 256-thread groups of the per-code kernels (order 1)
+    // codes longer than 1024 keep L in a slot per wavefront of the single
+    // kernel (order 0); in the per-code kernels (order 1) N = 2048 and 4096
+    // decode on chip and longer codes use the slots of their 256-thread
+    // groups
     if (max_long) {
         p->slot_floats = (int64_t)(max_long + 1) << max_long;
         p->slots = waves;

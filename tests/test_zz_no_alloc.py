@@ -35,6 +35,9 @@ CASES = [
                                     freeze_walk=0)),
     (64, 32, 2.5, 500, 37, dict(max_iter=40, early_stop=True, freezing=False,
                                 freeze_input=1, freeze_walk=0)),
+    # message state in the static array's slots
+    (8192, 4096, 2.5, 40, 9, dict(max_iter=20, early_stop=True, freezing=True,
+                                  freeze_input=1, freeze_walk=0)),
 ]
 
 
