@@ -58,8 +58,9 @@ TRAFFIC_RECORDS = {
                  _csrc("pbp_unrolled.hip")),
     # the mixed batch's N = 4096 frames decoded alone: three class kernels
     # (one per rate) per decode, summed
-    "mixed": ("traffic_class_wg_n4096_mixed.txt",
-              _csrc("pbp_mixed.hip", "pbp_generic_decoder.h")),
+    "mixed": ("traffic_class_pair_n4096_mixed.txt",
+              _csrc("pbp_mixed.hip", "pbp_pair_decoder.h",
+                    "pbp_generic_decoder.h")),
 }
 KERNEL_SRCS = TRAFFIC_RECORDS["n1024"][1]
 
@@ -76,6 +77,7 @@ TRACE_RECORDS = {
     "sc": ("sc_decode_n1024_trace.md", _csrc("pbp_sc.hip")),
     "quant": ("quant_decode_n1024_3db_trace.md", _csrc("pbp_quant.hip")),
     "round_trip": ("round_trip_trace.md", _csrc("pbp_roundtrip.hip")),
+    "mixed": ("mixed_trace.md", TRAFFIC_RECORDS["mixed"][1]),
 }
 COUNTER_RECORDS = {
     "n1024": ("counters_bp_decode_r10_n1024_3db.md", KERNEL_SRCS),
@@ -196,11 +198,14 @@ def measured_traffic(workload="n1024", frames=None):
 
 
 def traced_kernel_ms(workload, kernel, frames):
-    """The average duration (ms) of `kernel`'s dispatches in the workload's
-    committed kernel trace, or None (missing, stale or other frames)."""
+    """The duration (ms) of `kernel` per launch of the workload in its
+    committed kernel trace (the average dispatch times the dispatches one
+    launch makes), or None (missing, stale or other frames)."""
     name, srcs = TRACE_RECORDS[workload]
-    v = _record_float(_record(name, srcs, frames), f"avg_ns[{kernel}]")
-    return None if v is None else v / 1e6
+    rec = _record(name, srcs, frames)
+    v = _record_float(rec, f"avg_ns[{kernel}]")
+    n = _record_float(rec, f"dispatches_per_launch[{kernel}]") or 1.0
+    return None if v is None else v * n / 1e6
 
 
 def valu_issue(workload, kernel, frames, ms):
@@ -973,9 +978,10 @@ def bench_mixed(args, pbp, torch):
         plan, d_cof_long, d_lo, d_io, d_llr, opts=opts, out=out), steps, 1)
     pe_long = pe[sel]
     it_long = iters[sel].astype(np.float64)
-    long_bytes = 16.0 * pe_long.sum() + 4.0 * 4096 * it_long.sum() + \
-        float(Ks[sel].sum()) + 12.0 * sel.sum()
+    # messages stay on chip: the channel is read once per frame
+    long_bytes = 4.0 * 4096 * sel.sum() + float(Ks[sel].sum()) + 12.0 * sel.sum()
     long_gbs = long_bytes / (ms_long / 1e3) / 1e9
+    long_ops = OPS_PER_PE * pe_long.sum() / (ms_long / 1e3) / 1e12
     return _line(
         "decoded info Mbit/s, mixed N in {256,1024,4096} x R in "
         "{1/3,1/2,5/6}, Eb/N0 U[1,4] dB", round(nbits / ms / 1e3, 2),
@@ -990,15 +996,12 @@ def bench_mixed(args, pbp, torch):
         eager_ms_per_step=round(ms_eager, 3), schedules=schedules,
         avg_iters=round(float(iters.mean()), 3),
         pe_per_frame=round(float(pe.mean()), 1), fer=errs / B,
-        roofline={"bound": "hbm", "achieved": round(long_gbs, 1),
-                  "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                  "frac": round(long_gbs / HBM_PEAK_GBS, 4),
-                  "traffic": measured_traffic("mixed", B),
-                  "kernel": "class_wg_kernel<12> (the three N = 4096 codes)",
-                  "kernel_ms": round(ms_long, 4),
-                  "note": "16 B per active PE (L state in device memory) "
-                          "plus 4N B of channel per iteration, N = 4096 "
-                          "frames decoded alone"},
+        roofline=dict(
+            _alu_roofline(long_ops, "mixed", "class_pair_kernel<12>", B,
+                          ms_long, "12 operations per PE activation of the "
+                          "N = 4096 frames decoded alone (three launches, "
+                          "one per rate, messages on chip)"),
+            hbm_gbs=round(long_gbs, 1)),
         step_valu={"achieved": round(ops, 3),
                    "peak": round(VALU_PEAK_TOPS, 3), "unit": "TOP/s",
                    "frac": round(ops / VALU_PEAK_TOPS, 4)},
