@@ -78,6 +78,7 @@ TRACE_RECORDS = {
     "quant": ("quant_decode_n1024_3db_trace.md", _csrc("pbp_quant.hip")),
     "round_trip": ("round_trip_trace.md", _csrc("pbp_roundtrip.hip")),
     "mixed": ("mixed_trace.md", TRAFFIC_RECORDS["mixed"][1]),
+    "unrolled": ("unrolled_trace.md", TRAFFIC_RECORDS["unrolled"][1]),
 }
 COUNTER_RECORDS = {
     "n1024": ("counters_bp_decode_r10_n1024_3db.md", KERNEL_SRCS),
@@ -1166,7 +1167,9 @@ def bench_unrolled(args, pbp, torch):
                   "frac": round(bwd_gbs / HBM_PEAK_GBS, 4),
                   "traffic": measured_traffic("unrolled", B),
                   "kernel": "unrolled_backward_kernel<10>",
-                  "kernel_ms": round(bwd_ms, 4),
+                  "kernel_ms": _round(traced_kernel_ms(
+                      "unrolled", "unrolled_backward_kernel<10>", B), 4),
+                  "event_ms": round(bwd_ms, 4),
                   "note": "checkpoint reads (T x B x (m-1) x N x 4 B), LLR "
                           "and output-gradient reads, gradient writes"},
         forward_roofline={"bound": "hbm", "achieved": round(fwd_gbs, 1),

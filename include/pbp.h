@@ -343,8 +343,7 @@ int32_t pbp_unrolled_forward(const pbp_code *code, const float *llr, int64_t B,
  * gradient.
  *   llr, alpha, T  as given to the forward call
  *   ckpt           device, the forward call's checkpoints (NULL if N = 2);
- *                  consumed: the call overwrites them with adjoints, so a
- *                  second backward call needs a new forward call
+ *                  read only (the adjoint state stays on chip)
  *   dout           device, B x N FP32, the gradient at the output
  *   dalpha_frame   device, B x T x m x 2 FP32, written: each frame's
  *                  contribution to the scale gradient (workspace owned by
@@ -355,7 +354,7 @@ int32_t pbp_unrolled_forward(const pbp_code *code, const float *llr, int64_t B,
  * Errors: as pbp_unrolled_forward. */
 int32_t pbp_unrolled_backward(const pbp_code *code, const float *llr,
                               int64_t B, int32_t T, const float *alpha,
-                              float *ckpt, const float *dout,
+                              const float *ckpt, const float *dout,
                               float *dalpha_frame, float *dalpha, float *dllr,
                               void *stream);
 

@@ -100,7 +100,7 @@ struct BwdParams {
     int T;
     const float *alpha;
     const uint64_t *frozen;
-    float *ckpt;              // read, then overwritten with L adjoints
+    const float *ckpt;        // L checkpoints, read only
     const float *dout;        // B x N
     float *dalpha_frame;      // B x T x m x 2
     float *dllr;              // B x N, or null
@@ -112,11 +112,13 @@ size_t fwd_lds_bytes()
     return sizeof(float) * (size_t)(M + 2) * Shape<M>::N;
 }
 
+// [adjoint of L, columns 2..m][R, two columns][adjoint of R, two columns]
+// [partial scale sums]
 template <int M>
 size_t bwd_lds_bytes()
 {
     using S = Shape<M>;
-    return sizeof(float) * ((size_t)(M + 2) * S::N + (size_t)M * S::NW * 2);
+    return sizeof(float) * ((size_t)(M + 3) * S::N + (size_t)M * S::NW * 2);
 }
 
 // Barrier that orders LDS only (device-memory accesses of a stage are
@@ -222,21 +224,26 @@ __global__ __launch_bounds__(Shape<M>::NT) void unrolled_forward_kernel(FwdParam
 
 
 // Backward pass.  L^{t-1} is read once from the checkpoint of iteration t
-// (device memory), by the recompute of the R sweep, and kept in registers
-// for the adjoint stages; the adjoint of L^{t-1} is written over the
-// checkpoint: stage j replaces rows a, b of column j+1 (read by this thread
-// only) with their adjoints, which iteration t-1 reads.  LDS holds only R^t
-// (columns 1..m) and two columns of its adjoint (about 49 KB at m = 10), and
-// at most 80 VGPRs keep six wavefronts per SIMD, so three groups of eight
-// wavefronts fit on a compute unit.
+// (device memory) and R^t is recomputed from it; each thread keeps the L
+// and R inputs of its PE at every stage in registers for the adjoint stages
+// (the same rows), so R needs only two LDS columns in turn.  The adjoint of
+// L (columns 2..m) stays in LDS across iterations: stage j reads the
+// adjoint of L^t at column j and then writes that of L^{t-1} at column j+1
+// over the values stage j+1 read, so device memory sees only the
+// checkpoints, the LLRs and the gradients.  LDS: m + 3 columns (53 KB at
+// m = 10); at most 102 VGPRs (no spills) keep five wavefronts per SIMD, so
+// two groups of eight wavefronts per compute unit, and the grid is sized to
+// what is resident.
 template <int M>
-__global__ __launch_bounds__(Shape<M>::NT, 6) void unrolled_backward_kernel(BwdParams P)
+__global__ __launch_bounds__(Shape<M>::NT, 5) void unrolled_backward_kernel(BwdParams P)
 {
     using S = Shape<M>;
     constexpr int N = S::N, H = S::H, NT = S::NT, NW = S::NW;
     extern __shared__ __align__(16) float sm[];
-    float *Rc = sm;                     // R^t, column c (1..m) at (c-1)*N
-    float *dR = Rc + M * N;             // adjoint of R, two columns by parity
+    float *dA = sm;                     // adjoint of L, column c (2..m) at
+                                        // (c-2)*N
+    float *Rc = dA + (M - 1) * N;       // R^t, two columns by parity
+    float *dR = Rc + 2 * N;             // adjoint of R, two columns by parity
     float *red = dR + 2 * N;            // [m][NW][2] wavefront partial sums
     const int tid = (int)threadIdx.x;
     const int lane = tid & 63, wv = tid >> 6;
@@ -252,13 +259,12 @@ __global__ __launch_bounds__(Shape<M>::NT, 6) void unrolled_backward_kernel(BwdP
             dv[k] = i < N ? P.dout[f * N + i] : 0.0f;
             dc[k] = 0.0f;
         }
+        // the adjoint of L after the last iteration is zero
+        for (int i = tid; i < (M - 1) * N; i += NT)
+            dA[i] = 0.0f;
         for (int t = P.T - 1; t >= 0; t--) {
-            // L^{t-1} at columns 2..m, replaced by its adjoint below
-            float *ck = P.ckpt + ((int64_t)t * P.B + f) * (M - 1) * N;
-            // adjoint of L^t at columns 2..m (zero after the last iteration)
-            const float *dk = t + 1 < P.T
-                                  ? P.ckpt + ((int64_t)(t + 1) * P.B + f) * (M - 1) * N
-                                  : nullptr;
+            // L^{t-1} at columns 2..m
+            const float *ck = P.ckpt + ((int64_t)t * P.B + f) * (M - 1) * N;
             auto lprev = [&](int c, int r) -> float {
                 return c == M + 1 ? (frozen_at(P.frozen, r) ? kInf : 0.0f)
                                   : ck[(c - 2) * N + r];
@@ -293,22 +299,37 @@ __global__ __launch_bounds__(Shape<M>::NT, 6) void unrolled_backward_kernel(BwdP
                     Rc[i] = yv[k];
             }
             sync_lds();
+            // R^t at column j on this thread's rows of stage j, kept for the
+            // adjoint stages (column j at parity (j - 1) & 1)
+            float keepRa[M], keepRb[M];
 #pragma unroll
             for (int j = 1; j < M; j++) {
                 const float aR = scale_at(P.alpha, ((int64_t)t * M + (j - 1)) * 2 + 1);
                 const int sh = M - j, h = 1 << sh;
+                keepRa[j - 1] = 0.0f;
+                keepRb[j - 1] = 0.0f;
                 if (tid < H) {
                     const int a = row_a(j);
                     const int b = a + h;
-                    const float *Ri = Rc + (j - 1) * N;
-                    float *Ro = Rc + j * N;
+                    const float *Ri = Rc + ((j - 1) & 1) * N;
+                    float *Ro = Rc + (j & 1) * N;
                     const float La = keepLa[j - 1], Lb = keepLb[j - 1];
                     const float Ra = Ri[a], Rb = Ri[b];
+                    keepRa[j - 1] = Ra;
+                    keepRb[j - 1] = Rb;
                     const float s = Lb + Rb;
                     Ro[a] = aR * g0(Ra, s);
                     Ro[b] = Rb + aR * g0(La, Ra);
                 }
                 sync_stages<NW>(h, h >> 1);
+            }
+            keepRa[M - 1] = 0.0f;
+            keepRb[M - 1] = 0.0f;
+            if (tid < H) {
+                const int a = row_a(M);
+                const float *Ri = Rc + ((M - 1) & 1) * N;
+                keepRa[M - 1] = Ri[a];
+                keepRb[M - 1] = Ri[a + 1];
             }
             {
                 float *d = dR + ((M + 1) & 1) * N;
@@ -320,20 +341,17 @@ __global__ __launch_bounds__(Shape<M>::NT, 6) void unrolled_backward_kernel(BwdP
                 }
             }
             sync_lds();
-            // the input from device memory of stage j (the adjoint of L^t at
-            // column j), one stage ahead
+            // the adjoint of L^t at column j, stage j's input (LDS)
             float qiLa = 0.0f, qiLb = 0.0f;
             auto fetch = [&](int j) {
                 const int a = row_a(j), b = a + (1 << (M - j));
                 qiLa = 0.0f;
                 qiLb = 0.0f;
-                if (j >= 2 && dk) {
-                    qiLa = dk[(j - 2) * N + a];                   // column j
-                    qiLb = dk[(j - 2) * N + b];
+                if (j >= 2) {
+                    qiLa = dA[(j - 2) * N + a];                   // column j
+                    qiLb = dA[(j - 2) * N + b];
                 }
             };
-            if (tid < H)
-                fetch(M);
 #pragma unroll
             for (int j = M; j >= 1; j--) {
                 const float aL = scale_at(P.alpha, ((int64_t)t * M + (j - 1)) * 2);
@@ -343,19 +361,16 @@ __global__ __launch_bounds__(Shape<M>::NT, 6) void unrolled_backward_kernel(BwdP
                 if (tid < H) {
                     const int a = row_a(j);
                     const int b = a + h;
-                    const float *Ri = Rc + (j - 1) * N;
                     const float *dRi = dR + ((j + 1) & 1) * N;   // column j+1
                     float *dRo = dR + (j & 1) * N;               // column j
                     // L^{t-1} at column j+1: kept from the R sweep, or the
                     // frozen prior at column m+1
                     const float La = j < M ? keepLa[j - 1] : lprev(M + 1, a);
                     const float Lb = j < M ? keepLb[j - 1] : lprev(M + 1, b);
+                    fetch(j);
                     const float iLa = qiLa, iLb = qiLb;
                     float oLa = 0.0f, oLb = 0.0f;
-                    // stage j-1 reads column j, which this stage leaves as is
-                    if (j > 1)
-                        fetch(j - 1);
-                    const float Ra = Ri[a], Rb = Ri[b];
+                    const float Ra = keepRa[j - 1], Rb = keepRb[j - 1];
                     const float s = Lb + Rb;
                     const float gA = g0(La, s), g1 = g0(La, Ra), gB = g0(Ra, s);
                     // adjoints of the four outputs; infinite outputs are constants
@@ -385,10 +400,11 @@ __global__ __launch_bounds__(Shape<M>::NT, 6) void unrolled_backward_kernel(BwdP
                         dRb += ds;
                     }
                     if (j + 1 <= M) {
-                        // column j+1 of L^{t-1} is read by this stage only,
-                        // and only by this thread: its adjoint takes its place
-                        ck[(j - 1) * N + a] = finite(La) ? dLa : 0.0f;
-                        ck[(j - 1) * N + b] = finite(Lb) ? dLb : 0.0f;
+                        // the adjoint of L^{t-1} at column j+1 replaces that
+                        // of L^t there, which stage j+1 read before the
+                        // barrier
+                        dA[(j - 1) * N + a] = finite(La) ? dLa : 0.0f;
+                        dA[(j - 1) * N + b] = finite(Lb) ? dLb : 0.0f;
                     }
                     dRo[a] = dRa;
                     dRo[b] = dRb;
@@ -427,8 +443,8 @@ __global__ __launch_bounds__(Shape<M>::NT, 6) void unrolled_backward_kernel(BwdP
                     acc += red[((tid >> 1) * NW + w) * 2 + (tid & 1)];
                 P.dalpha_frame[((f * P.T + t) * M) * 2 + tid] = acc;
             }
-            // the adjoints written over this iteration's checkpoint are read
-            // by other threads in the next one
+            // the adjoint of L written in this iteration is read by other
+            // threads in the next one
             __syncthreads();
         }
         if (P.dllr) {
@@ -495,7 +511,17 @@ hipError_t launch_backward(const pbp_code *c, BwdParams &P, hipStream_t st)
                                        (int)lds);
     if (e != hipSuccess)
         return e;
-    hipLaunchKernelGGL(kern, dim3((unsigned)frames_grid(c, P.B, 3)),
+    // as many groups per compute unit as are resident (a grid stride over
+    // more would leave the extra groups a tail of their own)
+    static int occ = 0;
+    if (occ < 1) {
+        int o = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&o, (const void *)kern,
+                                                         Shape<M>::NT, lds) != hipSuccess)
+            return hipGetLastError();
+        occ = o < 1 ? 1 : o;
+    }
+    hipLaunchKernelGGL(kern, dim3((unsigned)frames_grid(c, P.B, occ)),
                        dim3(Shape<M>::NT), lds, st, P);
     return hipGetLastError();
 }
@@ -567,7 +593,7 @@ extern "C" int32_t pbp_unrolled_forward(const pbp_code *code, const float *llr,
 
 extern "C" int32_t pbp_unrolled_backward(const pbp_code *code, const float *llr,
                                          int64_t B, int32_t T,
-                                         const float *alpha, float *ckpt,
+                                         const float *alpha, const float *ckpt,
                                          const float *dout, float *dalpha_frame,
                                          float *dalpha, float *dllr,
                                          void *stream)
