@@ -14,6 +14,12 @@
 // [x_left ^ x_right | x_right] by n XORs.  Leaf i follows leaf i - 1 by one
 // g step at the depth where the path turns right (the depth of the lowest
 // set bit of i) and f steps down to the leaf.
+//
+// From N = 64 on, the bottom six levels run in registers: the subtrees of 64
+// positions are the leaves of the LDS walk above, and each is decoded with
+// one position per lane, its node LLRs moving between lanes by DPP and
+// cross-lane shuffles and its re-encoded bits in one 64-bit mask, every
+// index known at compile time.  The arithmetic is the same f and g.
 #include <hip/hip_runtime.h>
 
 #include "pbp_internal.h"
@@ -52,6 +58,7 @@ struct SCParams {
     float *leaf_out;                // B x N or null: the LLR at each leaf
 };
 
+// N < 64: every level in LDS
 template <int M>
 __global__ __launch_bounds__(64) void sc_decode_kernel(SCParams P)
 {
@@ -123,23 +130,199 @@ __global__ __launch_bounds__(64) void sc_decode_kernel(SCParams P)
     }
 }
 
+
+// node LLRs held one per lane: lane j (< n) takes lane j + n
+template <int n>
+__device__ __forceinline__ float from_lane_plus(float v)
+{
+    if constexpr (n <= 8) {
+        // row_shl:n within each row of 16 lanes (lanes j < n stay in row 0)
+        return __int_as_float(__builtin_amdgcn_update_dpp(
+            0, __float_as_int(v), 0x100 | n, 0xf, 0xf, false));
+    } else {
+        return __shfl_down(v, n, 64);
+    }
+}
+
+// The 64 positions of one subtree, root LLRs a0 (lane i = position i):
+// decisions and leaf LLRs in position order, re-encoded bits returned as a
+// mask (bit i = x_i of x = u G_64).  fz: the subtree's frozen bits.  Leaf
+// i's LLR is written to leaf (when not null) by lane 0.
+struct Sub64 {
+    float a[7];           // the current path's node LLRs, level k has 64 >> k
+    uint64_t x;           // decided, then re-encoded bits
+    uint64_t fz;
+    float *leaf;
+    int lane;
+
+    // level K+1 from level K: left child (f) or right child (g)
+    template <int K>
+    __device__ __forceinline__ void step_f()
+    {
+        constexpr int n = 32 >> K;           // child size
+        const float b = from_lane_plus<n>(a[K]);
+        a[K + 1] = sc_f(a[K], b);
+    }
+    template <int K, int I>
+    __device__ __forceinline__ void step_g()
+    {
+        constexpr int n = 32 >> K;           // child size; left sibling at
+                                             // positions I - n .. I - 1
+        const float b = from_lane_plus<n>(a[K]);
+        const uint8_t c = (uint8_t)((x >> (I - n)) >> lane) & 1;
+        a[K + 1] = sc_g(a[K], b, c);
+    }
+    template <int K, int I>
+    __device__ __forceinline__ void down_f()
+    {
+        if constexpr (K < 6) {
+            step_f<K>();
+            down_f<K + 1, I>();
+        }
+    }
+    template <int I>
+    __device__ __forceinline__ void leaf_step()
+    {
+        if constexpr (I < 64) {
+            if constexpr (I == 0) {
+                down_f<0, 0>();
+            } else {
+                constexpr int t = __builtin_ctz(I);
+                constexpr int K = 5 - t;          // level of the turning node
+                step_g<K, I>();
+                down_f<K + 1, I>();
+            }
+            // leaf decision: 0 at a frozen position, else [LLR < 0]
+            const float lv = __int_as_float(__builtin_amdgcn_readfirstlane(
+                __float_as_int(a[6])));
+            const bool u = !((fz >> I) & 1) && lv < 0.0f;
+            if (leaf && lane == 0)
+                leaf[I] = lv;
+            x |= (uint64_t)u << I;
+            // completed right subtrees: [x_l ^ x_r | x_r]
+#pragma unroll
+            for (int tt = 0; tt < 6; tt++) {
+                if (((I >> tt) & 1) == 0)
+                    break;
+                const int n = 1 << tt;
+                const int s0 = I + 1 - 2 * n;
+                const uint64_t m = (n == 64 ? ~0ull : ((1ull << n) - 1)) << s0;
+                x ^= (x >> n) & m;
+            }
+            leaf_step<I + 1>();
+        }
+    }
+};
+
+// N >= 64: the levels above the 64-position subtrees in LDS, the subtrees in
+// registers
 template <int M>
-hipError_t launch_sc(const pbp_code *c, SCParams &P, hipStream_t st)
+__global__ __launch_bounds__(64) void sc_decode64_kernel(SCParams P)
 {
     constexpr int N = 1 << M;
-    const size_t lds = sizeof(float) * N + N;
-    int64_t grid = P.B;
-    const int64_t cap = (int64_t)c->cus * 32;
-    if (grid > cap)
-        grid = cap;
-    auto kern = sc_decode_kernel<M>;
+    constexpr int MS = M - 6;                 // depth of the 64-position nodes
+    extern __shared__ __align__(16) unsigned char smem[];
+    float *alpha = reinterpret_cast<float *>(smem);          // N - 1 floats
+    uint8_t *beta = smem + sizeof(float) * N;                // N bytes
+    const int lane = (int)threadIdx.x;
+
+    for (int64_t frame = blockIdx.x; frame < P.B; frame += gridDim.x) {
+        const float *ch = P.llr + frame * N;
+        auto col = [&](int d) -> float * { return alpha + (N - (N >> (d - 1))); };
+        for (int s = 0; s < (N >> 6); s++) {
+            // the path to subtree s: one g step where it turns right, f steps
+            // down to depth MS (every node there has at least 128 positions)
+            int p = 0;
+            if (s > 0) {
+                const int t = __builtin_ctz(s) + 6;
+                p = M - 1 - t;
+                const int n = 1 << t;
+                const float *src = p == 0 ? ch : col(p);
+                float *dst = col(p + 1);
+                const uint8_t *c = beta + (64 * s - n);
+                for (int j = lane; j < n; j += 64)
+                    dst[j] = sc_g(src[j], src[j + n], c[j]);
+                wave_sync();
+                p++;
+            }
+            for (int d = p; d < MS; d++) {
+                const int n = N >> (d + 1);
+                const float *src = d == 0 ? ch : col(d);
+                float *dst = col(d + 1);
+                for (int j = lane; j < n; j += 64)
+                    dst[j] = sc_f(src[j], src[j + n]);
+                wave_sync();
+            }
+            Sub64 sub;
+            sub.a[0] = MS == 0 ? ch[lane] : col(MS)[lane];
+            sub.x = 0;
+            sub.fz = P.frozen_words[s];
+            sub.leaf = P.leaf_out ? P.leaf_out + frame * N + 64 * s : nullptr;
+            sub.lane = lane;
+            sub.leaf_step<0>();
+            beta[64 * s + lane] = (uint8_t)((sub.x >> lane) & 1);
+            wave_sync();
+            // completed right subtrees above the 64-position level
+            for (int t = 6; t < M && ((s >> (t - 6)) & 1); t++) {
+                const int n = 1 << t;
+                const int s0 = 64 * (s + 1) - 2 * n;
+                for (int j = lane; j < n; j += 64)
+                    beta[s0 + j] ^= beta[s0 + n + j];
+                wave_sync();
+            }
+        }
+        // beta holds x = u G; the decided source bits are its transform
+        for (int h = 1; h < N; h <<= 1) {
+            for (int q = lane; q < N / 2; q += 64) {
+                const int a = ((q / h) * 2 * h) + (q % h);
+                beta[a] ^= beta[a + h];
+            }
+            wave_sync();
+        }
+        uint8_t *out = P.info_out + frame * P.K;
+        for (int k = lane; k < P.K; k += 64)
+            out[k] = beta[P.info_pos[k]];
+        wave_sync();
+    }
+}
+
+// as many wavefronts per compute unit as are resident (occ, looked up once
+// per kernel): a grid stride over more would leave the extra ones a tail
+template <class Kern>
+hipError_t launch_k(Kern kern, const pbp_code *c, SCParams &P, size_t lds,
+                    int &occ, hipStream_t st)
+{
     hipError_t e = hipFuncSetAttribute((const void *)kern,
                                        hipFuncAttributeMaxDynamicSharedMemorySize,
                                        (int)lds);
     if (e != hipSuccess)
         return e;
+    if (occ < 1) {
+        int o = 0;
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&o, (const void *)kern,
+                                                         64, lds);
+        if (e != hipSuccess)
+            return e;
+        occ = o < 1 ? 1 : o;
+    }
+    int64_t grid = P.B;
+    const int64_t cap = (int64_t)c->cus * occ;
+    if (grid > cap)
+        grid = cap;
     hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(64), lds, st, P);
     return hipGetLastError();
+}
+
+template <int M>
+hipError_t launch_sc(const pbp_code *c, SCParams &P, hipStream_t st)
+{
+    constexpr int N = 1 << M;
+    const size_t lds = sizeof(float) * N + N;
+    static int occ = 0;
+    if constexpr (M >= 6)
+        return launch_k(sc_decode64_kernel<M>, c, P, lds, occ, st);
+    else
+        return launch_k(sc_decode_kernel<M>, c, P, lds, occ, st);
 }
 
 }  // namespace
