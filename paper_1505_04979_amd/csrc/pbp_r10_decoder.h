@@ -24,9 +24,12 @@
 // live in LDS; R crosses a group boundary through an LDS transpose.  The
 // hard decisions of the CSFG checks (eqs. (2)-(4)) and of the G-matrix stop
 // are ballot words (bit = lane) per register; the transform by F^{(x)s} is
-// word XORs along free register bits and shift/mask/XOR along free lane
-// bits, in scalar registers.  Stages 1 and 10 share mapping MA, so the stop
-// compares u G with the channel-side decisions without any reshuffle.
+// word XORs along free register bits, and along the lane bits each lane
+// reads its own output as a parity over the word (two ANDs and two
+// popcounts, in every lane at once).  A stage's check reads only the
+// selected block's registers, through a branch tree ending in one ballot.
+// Stages 1 and 10 share mapping MA, so the stop compares u G with the
+// channel-side decisions without any reshuffle.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -68,13 +71,13 @@ __device__ constexpr uint64_t kLaneSet[6] = {
     0xAAAAAAAAAAAAAAAAull, 0xCCCCCCCCCCCCCCCCull, 0xF0F0F0F0F0F0F0F0ull,
     0xFF00FF00FF00FF00ull, 0xFFFF0000FFFF0000ull, 0xFFFFFFFF00000000ull};
 
-__device__ __forceinline__ uint64_t lane_clr(int b) { return ~kLaneSet[b]; }
-
-// butterfly of the lane-index bit b over a ballot word: lane i with bit b
-// clear takes bit i ^ bit (i + 2^b)
-__device__ __forceinline__ uint64_t ffx_lane(uint64_t w, int b)
+// a uniform bound the compiler may not fold back into per-lane operands
+// (lane >= bound - c would otherwise become lane + c >= bound, with one
+// live register per c)
+__device__ __forceinline__ int opaque_s(int v)
 {
-    return w ^ ((w >> (1 << b)) & lane_clr(b));
+    asm volatile("" : "+s"(v));
+    return v;
 }
 
 __device__ __forceinline__ uint64_t ballot(bool p)
@@ -166,6 +169,9 @@ struct Decoder {
     // whether the row of register q in mapping mp is frozen on this lane
     // (two registers, so the checks need no scalar loads and their waits)
     uint32_t fzb[2];
+    // lanes whose index contains this lane's index bits (bit l of
+    // sup_hi:sup_lo): the lane part of the transform by F^{(x)s}
+    uint32_t sup_lo, sup_hi;
 
     // frozen ballot word [mapping mp][register q] as stored by the host
     __device__ __forceinline__ uint64_t fz_word(int mp, int q) const
@@ -179,12 +185,6 @@ struct Decoder {
     __device__ __forceinline__ bool fzbit(int mp, int q) const
     {
         return (fzb[mp >> 1] >> ((mp & 1) * 16 + q)) & 1;
-    }
-
-    // frozen ballot word [mapping mp][register q] (bit l: lane l's row)
-    __device__ __forceinline__ uint64_t fz(int mp, int q) const
-    {
-        return ballot(fzbit(mp, q));
     }
 
     __device__ __forceinline__ Decoder(const Params &P_, Smem &S_, int lane_)
@@ -208,6 +208,13 @@ struct Decoder {
                 b |= (uint32_t)((fz_word(2 * h + k / Q, k % Q) >> lane) & 1) << k;
             fzb[h] = b;
         }
+        uint64_t sup = ~0ull;
+#pragma unroll
+        for (int lb = 0; lb < 6; lb++)
+            if ((lane >> lb) & 1)
+                sup &= kLaneSet[lb];
+        sup_lo = (uint32_t)sup;
+        sup_hi = (uint32_t)(sup >> 32);
     }
 
     template <int MP>
@@ -244,9 +251,10 @@ struct Decoder {
         if (FRZ) {
             const int rq = rowq(MA, q);
             if (rq + 252 >= lo && rq < hi) {
-                const int r = row<MA>(q);
-                if (r >= lo && r < hi)
-                    v = S.dec[r] ? -kInf : kInf;
+                // row >= lo and row < hi, compared as the lane part against
+                // uniform bounds (no per-register row value stays live)
+                if (lr[MA] >= opaque_s(lo - rq) && lr[MA] < opaque_s(hi - rq))
+                    v = S.dec[row<MA>(q)] ? -kInf : kInf;
             }
         }
         return v;
@@ -329,7 +337,8 @@ struct Decoder {
     // One PE of eq. (1) on registers qa (row a) and qb = qa | BIT (row a + h).
     // Lin = L at column J+1; the outputs L at column J go to registers, to
     // LDS (boundary column) or into the channel-side decisions (J = 1).
-    template <int J, int QA>
+    // KEPT: stage M may read rows frozen at stage M (their kept decisions)
+    template <int J, int QA, bool KEPT>
     __device__ __forceinline__ void pe_update()
     {
         constexpr int MP = smap(J);
@@ -337,8 +346,8 @@ struct Decoder {
         const float alpha = P.alpha;
         float La, Lb;
         if constexpr (J == M) {
-            La = l11(QA, l11lo, l11hi);
-            Lb = l11(QB, l11lo, l11hi);
+            La = KEPT ? l11(QA, l11lo, l11hi) : l11(QA, 0, 0);
+            Lb = KEPT ? l11(QB, l11lo, l11hi) : l11(QB, 0, 0);
         } else {
             float *Lin = lreg<J + 1>();
             La = Lin[QA];
@@ -378,65 +387,73 @@ struct Decoder {
     static constexpr int slot_of(int qa) { return J == 2 ? (qa >> 3) * 2 : (qa >> 2); }
 
     // PEs of stage J in register slot SLOT, all lanes active
-    template <int J, int QA, int SLOT>
+    template <int J, int QA, int SLOT, bool KEPT>
     __device__ __forceinline__ void pe_slot()
     {
         if constexpr (QA < Q) {
             if constexpr (!((QA >> sqb(J)) & 1) && slot_of<J>(QA) == SLOT)
-                pe_update<J, QA>();
-            pe_slot<J, QA + 1, SLOT>();
+                pe_update<J, QA, KEPT>();
+            pe_slot<J, QA + 1, SLOT, KEPT>();
         }
     }
 
     // the same, each PE masked to the lanes whose row is >= f
-    template <int J, int QA, int SLOT>
+    template <int J, int QA, int SLOT, bool KEPT>
     __device__ __forceinline__ void pe_slot_masked(int f)
     {
         if constexpr (QA < Q) {
             if constexpr (!((QA >> sqb(J)) & 1) && slot_of<J>(QA) == SLOT) {
                 constexpr int MP = smap(J);
-                if (lr[MP] + rowq(MP, QA) >= f)
-                    pe_update<J, QA>();
+                if (lr[MP] >= opaque_s(f - rowq(MP, QA)))
+                    pe_update<J, QA, KEPT>();
             }
-            pe_slot_masked<J, QA + 1, SLOT>(f);
+            pe_slot_masked<J, QA + 1, SLOT, KEPT>(f);
         }
     }
 
-    template <int J, int SLOT>
-    __device__ __forceinline__ void run_slot() { pe_slot<J, 0, SLOT>(); }
+    template <int J, int SLOT, bool KEPT>
+    __device__ __forceinline__ void run_slot() { pe_slot<J, 0, SLOT, KEPT>(); }
 
     // Rows of slot s are [256 s, 256 s + 256).  Frozen prefix f: a slot
     // entirely >= f runs unmasked, the slot holding f runs masked per lane,
     // slots entirely below f are skipped.
-    template <int J, int SLOT>
+    template <int J, int SLOT, bool KEPT>
     __device__ __forceinline__ void slot_step(int f)
     {
         // the common case (nothing of the slot frozen) falls through
         if (__builtin_expect(f <= SLOT * 256, 1))
-            run_slot<J, SLOT>();
+            run_slot<J, SLOT, KEPT>();
         else if (f < SLOT * 256 + 256)
-            pe_slot_masked<J, 0, SLOT>(f);
+            pe_slot_masked<J, 0, SLOT, KEPT>(f);
     }
 
-    template <int J>
+    // With no frozen prefix at the stage (every stage while nothing is
+    // frozen, and stage 1 always) all slots run unmasked behind one branch.
+    template <int J, bool KEPT>
     __device__ __forceinline__ void stage_pes(int f)
     {
-        if constexpr (J == 1 || !FRZ) {
-            run_slot<J, 0>(); run_slot<J, 1>(); run_slot<J, 2>(); run_slot<J, 3>();
+        if (J == 1 || !FRZ || f == 0) {
+            run_slot<J, 0, KEPT>(); run_slot<J, 1, KEPT>();
+            run_slot<J, 2, KEPT>(); run_slot<J, 3, KEPT>();
         } else {
-            slot_step<J, 0>(f);
-            slot_step<J, 1>(f);
-            slot_step<J, 2>(f);
-            slot_step<J, 3>(f);
+            slot_step<J, 0, KEPT>(f);
+            slot_step<J, 1, KEPT>(f);
+            slot_step<J, 2, KEPT>(f);
+            slot_step<J, 3, KEPT>(f);
         }
     }
 
     // stage J runs (N - f) / 2 PEs: N / 2 less the prefix's f / 2, which is
-    // summed per iteration in 32 bits (at most M N / 2 a sweep)
+    // summed per iteration in 32 bits (at most M N / 2 a sweep).  Stage M
+    // consults the kept decisions only while some row frozen at stage M
+    // lies at or above its own frozen prefix (rarely, and for a row or two).
     template <int J>
     __device__ __forceinline__ void stage(int f)
     {
-        stage_pes<J>(f);
+        if (FRZ && J == M && l11hi > l11lo)
+            stage_pes<J, true>(f);
+        else
+            stage_pes<J, false>(f);
         if constexpr (FRZ && J > 1)
             pskip += p[J - 1] << (M - J);
     }
@@ -481,70 +498,122 @@ struct Decoder {
         }
     }
 
-    // check (and on success freeze) the block whose fixed register bits are
-    // T; lm selects the block's lanes.  Returns true when frozen.
-    template <int J, int T>
-    __device__ __forceinline__ bool check_block(uint64_t lm)
+    // The lane part of the transform by F^{(x)s}, read at this lane: output
+    // bit i of x F^{(x)s} is the XOR of the inputs whose index contains i,
+    // so along the lane-index bits it is the parity of the ballot word w over
+    // the lanes whose index contains this lane's (the mask sup).  A block's
+    // free lane bits are the low ones and w is zero outside the block, so the
+    // same mask serves every stage.  Returns the count; bit 0 is the parity.
+    __device__ __forceinline__ uint32_t lane_fx(uint64_t w) const
+    {
+        return (uint32_t)__builtin_popcount((uint32_t)w & sup_lo) +
+               (uint32_t)__builtin_popcount((uint32_t)(w >> 32) & sup_hi);
+    }
+
+    // lanes where the transformed word w is 1 at a frozen row of register q
+    // (uniform, run time) in mapping MP: eq. (4) fails on any of the block's
+    __device__ __forceinline__ uint64_t frozen_hits(int mp, uint64_t w, int q) const
+    {
+        const uint32_t f = fzb[mp >> 1] >> ((mp & 1) * 16 + q);
+        return ballot(((lane_fx(w) & f) & 1u) != 0u);
+    }
+
+    // candidates of a register branch tree: registers in [LO, HI) whose bits
+    // under CM equal CV
+    template <int CM, int CV, int LO, int HI>
+    static constexpr bool has_cand()
+    {
+        for (int q = LO; q < HI; q++)
+            if ((q & CM) == CV)
+                return true;
+        return false;
+    }
+
+    // eq. (2)'s decisions at register q of stage J as a ballot word; q is
+    // uniform and known at run time only, and is one of the registers whose
+    // bits under CM equal CV.  A branch tree over those candidates ends in
+    // one ballot per leaf, so only the selected register is read.
+    template <int J, int CM, int CV, int LO = 0, int HI = Q>
+    __device__ __forceinline__ uint64_t input_word(int q)
+    {
+        if constexpr (HI - LO == 1) {
+            return ballot(check_input<J>(LO) < 0.0f);
+        } else {
+            constexpr int MID = (LO + HI) / 2;
+            if constexpr (!has_cand<CM, CV, LO, MID>())
+                return input_word<J, CM, CV, MID, HI>(q);
+            else if constexpr (!has_cand<CM, CV, MID, HI>())
+                return input_word<J, CM, CV, LO, MID>(q);
+            else if (q < MID)
+                return input_word<J, CM, CV, LO, MID>(q);
+            else
+                return input_word<J, CM, CV, MID, HI>(q);
+        }
+    }
+
+    // row bits contributed by register index q (uniform, run time)
+    template <int MP>
+    static __device__ __forceinline__ int rowq_rt(int q)
+    {
+        return ((q & 1) << qrow(MP, 0)) | (((q >> 1) & 1) << qrow(MP, 1)) |
+               (((q >> 2) & 1) << qrow(MP, 2)) | (((q >> 3) & 1) << qrow(MP, 3));
+    }
+
+    // input words of the block's registers t | I other than t | FREE
+    template <int J, int I>
+    __device__ __forceinline__ void rest_words(int t, uint64_t lm, uint64_t *X0)
+    {
+        if constexpr (I < Q) {
+            constexpr int FREE = ~fixed_qmask<J>() & (Q - 1);
+            if constexpr ((I & FREE) == I && I != FREE)
+                X0[I] = input_word<J, FREE, I>(t | I) & lm;
+            rest_words<J, I + 1>(t, lm, X0);
+        }
+    }
+
+    // The rest of a block's check once its register with every free register
+    // bit set has passed (rare): the block's other registers t | i, eq. (3)
+    // along the free register bits as word XORs, eq. (4) per word, and on
+    // success the freeze.  wl is the passed word's input; lm the block's
+    // lanes.  Returns true when frozen.
+    template <int J>
+    __device__ __forceinline__ bool check_rest(int t, uint64_t lm, uint64_t wl)
     {
         constexpr int MP = smap(J);
-        constexpr int SH = M - J;
-        constexpr int FM = fixed_qmask<J>();
-        constexpr int QL = T | (~FM & (Q - 1));    // all free register bits set
-        uint64_t W[Q];
-        // the frozen word is requested first, so that its load overlaps the
-        // ballot and the transform
-        const uint64_t fzl = fz(MP, QL);
-        // eq. (2) as ballot words; the transform of word QL needs no other
-        // word, so eqs. (3)-(4) are tested on it first
-        W[QL] = ballot(check_input<J>(QL) < 0.0f) & lm;
-        {
-            uint64_t w = W[QL];
+        constexpr int FREE = ~fixed_qmask<J>() & (Q - 1);
+        uint64_t X0[Q], W[Q];
+        X0[FREE] = wl;
+        rest_words<J, 0>(t, lm, X0);
 #pragma unroll
-            for (int lb = 0; lb < 6; lb++)
-                if (lrow(MP, lb) < SH)
-                    w = ffx_lane(w, lb);
-            // most checks fail here
-            if (__builtin_expect((w & fzl) != 0, 1))
-                return false;
-        }
-#pragma unroll
-        for (int q = 0; q < Q; q++)
-            if ((q & FM) == T && q != QL)
-                W[q] = ballot(check_input<J>(q) < 0.0f) & lm;
-        // eq. (3) along the free register bits
+        for (int i = 0; i < Q; i++)
+            if ((i & FREE) == i)
+                W[i] = X0[i];
 #pragma unroll
         for (int qb = 0; qb < 4; qb++)
-            if (!((FM >> qb) & 1))
+            if ((FREE >> qb) & 1)
 #pragma unroll
-                for (int q = 0; q < Q; q++)
-                    if ((q & FM) == T && !((q >> qb) & 1))
-                        W[q] ^= W[q | (1 << qb)];
-        // eq. (3) along the free lane bits and eq. (4), word by word
-        bool bad = false;
+                for (int i = 0; i < Q; i++)
+                    if ((i & FREE) == i && !((i >> qb) & 1))
+                        W[i] ^= W[i | (1 << qb)];
+        uint64_t bad = 0;
 #pragma unroll
-        for (int q = 0; q < Q; q++) {
-            if ((q & FM) == T && !bad) {
-                uint64_t w = W[q];
-#pragma unroll
-                for (int lb = 0; lb < 6; lb++)
-                    if (lrow(MP, lb) < SH)
-                        w = ffx_lane(w, lb);
-                W[q] = w;
-                bad = (w & fz(MP, q)) != 0;
-            }
-        }
-        if (bad)
+        for (int i = 0; i < Q; i++)
+            if ((i & FREE) == i && i != FREE)
+                bad |= frozen_hits(MP, W[i], t | i);
+        if (bad & lm)
             return false;
         // freeze: keep uhat; when L at column J+1 lives in LDS, fix it to
         // (-1)^xhat inf there (register columns are fixed after the walk)
-        const bool mine = (lm >> lane) & 1;
+        if ((lm >> lane) & 1) {
 #pragma unroll
-        for (int q = 0; q < Q; q++) {
-            if ((q & FM) == T && mine) {
-                if constexpr (lbcol(J + 1) >= 0)
-                    S.lb[lbcol(J + 1)][lds_word<MP>(q)] =
-                        check_input<J>(q) < 0.0f ? -kInf : kInf;
-                S.dec[row<MP>(q)] = (uint8_t)((W[q] >> lane) & 1);
+            for (int i = 0; i < Q; i++) {
+                if ((i & FREE) == i) {
+                    const int rq = rowq_rt<MP>(t | i);
+                    S.dec[lr[MP] + rq] = (uint8_t)(lane_fx(W[i]) & 1u);
+                    if constexpr (lbcol(J + 1) >= 0)
+                        S.lb[lbcol(J + 1)][sl[MP] ^ swz(rq)] =
+                            ((X0[i] >> lane) & 1) ? -kInf : kInf;
+                }
             }
         }
         wave_sync();
@@ -564,29 +633,11 @@ struct Decoder {
             for (int q = 0; q < Q; q++) {
                 const int rq = rowq(MP, q);
                 if (rq + lanemax(MP) >= lo && rq < hi) {
-                    const int r = row<MP>(q);
                     const float fixed = check_input<J>(q) < 0.0f ? -kInf : kInf;
-                    Ln[q] = (r >= lo && r < hi) ? fixed : Ln[q];
+                    Ln[q] = (lr[MP] >= opaque_s(lo - rq) && lr[MP] < opaque_s(hi - rq))
+                                ? fixed : Ln[q];
                 }
             }
-        }
-    }
-
-    // binary dispatch over the fixed-register-bit values T in [LO, HI)
-    template <int J, int LO, int HI>
-    __device__ __forceinline__ bool dispatch(int t, uint64_t lm)
-    {
-        constexpr int FM = fixed_qmask<J>();
-        if constexpr (HI - LO == 1) {
-            if constexpr ((LO & FM) == LO)
-                return check_block<J, LO>(lm);
-            else
-                return false;
-        } else {
-            constexpr int MID = (LO + HI) / 2;
-            if (t < MID)
-                return dispatch<J, LO, MID>(t, lm);
-            return dispatch<J, MID, HI>(t, lm);
         }
     }
 
@@ -622,6 +673,7 @@ struct Decoder {
         constexpr int MP = smap(J);
         constexpr int SH = M - J;          // row bits below SH are free
         constexpr int FM = fixed_qmask<J>();
+        constexpr int FREE = ~FM & (Q - 1);
         // lanes inside block k.  In every stage's mapping the lane bits of
         // the fixed row bits are the top NF.. 5 and carry consecutive row
         // bits, so the block's lanes are one run of 2^NF lanes.
@@ -638,7 +690,13 @@ struct Decoder {
         for (int qb = 0; qb < 4; qb++)
             if ((FM >> qb) & 1)
                 t |= ((k >> (qrow(MP, qb) - SH)) & 1) << qb;
-        return dispatch<J, 0, 16>(t, lm);
+        // Along the register bits the output word of the block's register
+        // with every free bit set is its own input, so eqs. (3)-(4) are tested
+        // on it first; most checks fail there.
+        const uint64_t wl = input_word<J, FREE, FREE>(t | FREE) & lm;
+        if (__builtin_expect((frozen_hits(MP, wl, t | FREE) & lm) != 0, 1))
+            return false;
+        return check_rest<J>(t, lm, wl);
     }
 
     template <int J>
@@ -718,14 +776,8 @@ struct Decoder {
             return false;
         // G-matrix test: u F^{(x)10} == xhat.  Output word 15 (all register
         // bits set) depends on input word 15 alone: test it first.
-        {
-            uint64_t w = u_word(Q - 1, fm);
-#pragma unroll
-            for (int lb = 0; lb < 6; lb++)
-                w = ffx_lane(w, lb);
-            if (__builtin_expect(w != X[Q - 1], 1))
-                return false;
-        }
+        if (__builtin_expect(ballot(lane_fx(u_word(Q - 1, fm)) & 1u) != X[Q - 1], 1))
+            return false;
         uint64_t U[Q];
 #pragma unroll
         for (int q = 0; q < Q; q++)
@@ -736,18 +788,11 @@ struct Decoder {
             for (int q = 0; q < Q; q++)
                 if (!((q >> qb) & 1))
                     U[q] ^= U[q | (1 << qb)];
-        bool same = true;
+        uint64_t diff = 0;
 #pragma unroll
-        for (int q = 0; q < Q - 1; q++) {
-            if (same) {
-                uint64_t w = U[q];
-#pragma unroll
-                for (int lb = 0; lb < 6; lb++)
-                    w = ffx_lane(w, lb);
-                same = w == X[q];
-            }
-        }
-        return same;
+        for (int q = 0; q < Q - 1; q++)
+            diff |= ballot(lane_fx(U[q]) & 1u) ^ X[q];
+        return diff == 0;
     }
 
     __device__ __forceinline__ void write_outputs(int64_t frame, int iters)
