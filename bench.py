@@ -75,7 +75,8 @@ TRACE_RECORDS = {
     "n16384": ("n16384_trace.md",
                _csrc("pbp_decode.hip", "pbp_generic_decoder.h")),
     "sc": ("sc_decode_n1024_trace.md", _csrc("pbp_sc.hip")),
-    "quant": ("quant_decode_n1024_3db_trace.md", _csrc("pbp_quant.hip")),
+    "quant": ("quant_decode_n1024_3db_trace.md",
+              _csrc("pbp_quant.hip", "pbp_r10_decoder.h", "pbp_r10.h")),
     "round_trip": ("round_trip_trace.md", _csrc("pbp_roundtrip.hip")),
     "mixed": ("mixed_trace.md", TRAFFIC_RECORDS["mixed"][1]),
     "unrolled": ("unrolled_trace.md", TRAFFIC_RECORDS["unrolled"][1]),
@@ -768,7 +769,7 @@ def bench_sc(args, pbp, torch):
         bp_es_freeze_fer_ci95=list(wilson(bp_errs, B, z)),
         parity={"frames": S, "mismatched_frames": mism},
         roofline=_alu_roofline(
-            achieved, "sc", "sc_decode_kernel<10>", B, ms,
+            achieved, "sc", "sc_decode64_kernel<10>", B, ms,
             "2 m N operations per frame (m N / 2 f and m N / 2 g "
             "evaluations); one wavefront walks a frame's leaves in order"))
     if not args.no_cpu_baseline:
@@ -838,10 +839,14 @@ def bench_quant(args, pbp, torch):
         fer=errs / B, fer_ci95=list(wilson(errs, B, z)),
         fp32_fer=bp_errs / B, fp32_fer_ci95=list(wilson(bp_errs, B, z)),
         parity={"frames": S, "mismatched_frames": mism},
-        roofline=_alu_roofline(achieved, "quant", "quant_decode_kernel<10>",
-                               B, ms, "12 integer operations per PE "
-                               "activation"))
-    line["dtype"] = "i8"
+        roofline=_alu_roofline(achieved, "quant",
+                               "quant_r10_kernel<true, true>", B, ms,
+                               "12 operations per PE activation, as for FP32; "
+                               "the saturations and roundings come on top"),
+        messages="saturating 8-bit integers, carried exactly in FP32 "
+                 "registers")
+    # the integer messages are computed by FP32 instructions (exact here)
+    line["dtype"] = "f32"
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(
             llr_s, K, got["info"], {}, args.cpu_seconds, chunk=16,

@@ -192,12 +192,19 @@ int32_t pbp_decode_round_trip(const pbp_code *code, const float *llr,
  * sign sign ((a min(|x|, |y|) + 8) >> 4), a = round(16 alpha); its sums
  * saturate; +-Q replaces the +-inf of the frozen prior and of frozen CSFGs;
  * hard decisions take the exact sum's sign.  Same schedule, stop test,
- * freezing walk, iteration and PE counts as pbp_decode.
- *   bits      2..8 (messages are stored as bytes); frac 0..16
+ * freezing walk, iteration and PE counts as pbp_decode.  The scaled minimum
+ * itself is not saturated (above 1, alpha can lift it past Q).
+ *   bits      2..8; frac 0..16
  *   soft_out  device, B x N int8, or NULL: sat(R + L) at column m+1 (+-Q
  *             inside frozen CSFGs)
+ * N = 1024 runs pbp_decode's register-resident decoder, its integers held
+ * exactly in FP32 registers, and takes frames from the stream's workspace
+ * counter (calls on one stream are ordered, as for pbp_decode).  Other
+ * lengths keep every message as a byte in LDS, so they reject formats whose
+ * scaled minimum can exceed 127 (bits = 8 with alpha above 1.03).
  * Other arguments as pbp_decode.  N <= 4096.
- * Errors: as pbp_decode; PBP_EUNSUPPORTED for N > 4096. */
+ * Errors: as pbp_decode; PBP_EUNSUPPORTED for N > 4096, and for N != 1024
+ * with (round(16 alpha) Q + 8) >> 4 > 127. */
 int32_t pbp_decode_quant(const pbp_code *code, const float *llr, int64_t B,
                          const pbp_decode_opts *opts, int32_t bits,
                          int32_t frac, uint8_t *info_out, int32_t *iters_out,

@@ -2,25 +2,30 @@
 // pbp_decode (single sweep, G-matrix early stop, CSFG freezing) in the
 // integer arithmetic of a hardware decoder, the setting in which the paper
 // counts a PE's cost (Sections I and V).  Every message lies in [-Q, Q],
-// Q = 2^(b-1) - 1, and is stored as one signed byte; the channel is
-// clamp(round(LLR 2^F)); the scaled minimum of eq. (1) is
-// (a min(|x|, |y|) + 8) >> 4 with a = round(16 alpha); every sum of eq. (1)
-// saturates; +-Q stands for the +-inf of the frozen prior and of a frozen
-// CSFG's messages; hard decisions take the exact sum's sign.
+// Q = 2^(b-1) - 1; the channel is clamp(round(LLR 2^F)); the scaled minimum
+// of eq. (1) is (a min(|x|, |y|) + 8) >> 4 with a = round(16 alpha); every
+// sum of eq. (1) saturates; +-Q stands for the +-inf of the frozen prior and
+// of a frozen CSFG's messages; hard decisions take the exact sum's sign.
 //
-// One wavefront per frame, persistent over a grid stride, with the whole
-// state in LDS as bytes (L at columns 1..m+1, the working R column updated
-// in place stage by stage, the quantized channel, the kept decisions and
-// two bit-byte scratch columns): (m + 6) N bytes and the frozen prefixes,
-// 16 KB at N = 1024, a
-// quarter of the FP32 state.  PEs go four at a time where a stage's offset
-// is at least 4 (rows a..a+3 are one 32-bit LDS word in every column), one
-// at a time at the last two stages.  The CSFG check and the stop test
-// transform their decision bytes by F^{(x)s} in LDS, one butterfly level
-// per step.
+// N = 1024 runs the register-resident decoder of pbp_decode with the
+// fixed-point message arithmetic (pbp_r10_decoder.h, ArithFixed): messages
+// are integers held exactly in FP32 registers, so the PE is the FP32 one plus
+// a saturation per sum and a rounding per scaled minimum.
+//
+// Other lengths: one wavefront per frame, persistent over a grid stride,
+// with the whole state in LDS, one signed byte per message (L at columns
+// 1..m+1, the working R column updated in place stage by stage, the
+// quantized channel, the kept decisions and two bit-byte scratch columns):
+// (m + 6) N bytes and the frozen prefixes.  PEs go four at a time where a
+// stage's offset is at least 4 (rows a..a+3 are one 32-bit LDS word in every
+// column), one at a time at the last two stages.  The CSFG check and the
+// stop test transform their decision bytes by F^{(x)s} in LDS, one butterfly
+// level per step.
 #include <hip/hip_runtime.h>
 
 #include "pbp_internal.h"
+#include "pbp_r10.h"
+#include "pbp_r10_decoder.h"
 
 namespace {
 
@@ -282,6 +287,65 @@ hipError_t launch_quant(const pbp_code *c, QParams &P, hipStream_t st)
     return hipGetLastError();
 }
 
+// N = 1024: persistent wavefronts take frames from the stream's counter
+template <bool FRZ, bool ES>
+__global__ __launch_bounds__(64, 2) void quant_r10_kernel(pbp::r10::Params P)
+{
+    __shared__ pbp::r10::Smem S;
+    const int lane = (int)__builtin_amdgcn_workitem_id_x();
+    pbp::r10::Decoder<FRZ, ES, pbp::r10::ArithFixed> D(P, S, lane);
+    for (;;) {
+        int frame = 0;
+        if (lane == 0)
+            frame = atomicAdd(P.counter, 1);
+        frame = __shfl(frame, 0, 64);
+        if (frame >= P.B)
+            break;
+        D.decode(frame);
+    }
+    // the last wavefront out rewinds both counters for the next launch
+    if (lane == 0 && atomicAdd(P.counter + 1, 1) == (int)gridDim.x - 1) {
+        atomicExch(P.counter, 0);
+        atomicExch(P.counter + 1, 0);
+    }
+}
+
+hipError_t launch_quant_r10(const pbp_code *c, const QParams &Q, float alpha_q,
+                            int *counter, hipStream_t st)
+{
+    pbp::r10::Params P{};
+    P.llr = Q.llr;
+    P.B = Q.B;
+    P.counter = counter;
+    P.fzw = c->d_fzw10;
+    P.info_pos = Q.info_pos;
+    P.K = Q.K;
+    P.max_iter = Q.max_iter;
+    P.freezing = Q.freezing;
+    P.freeze_input = Q.freeze_input;
+    P.freeze_walk = Q.freeze_walk;
+    P.alpha = alpha_q;
+    P.info_out = Q.info_out;
+    P.iters_out = Q.iters_out;
+    P.pe_out = Q.pe_out;
+    P.soft_out = nullptr;
+    P.qmax = (float)Q.Q;
+    P.frac = Q.frac;
+    P.soft_q = Q.soft_out;
+    int64_t grid = (int64_t)c->cus * 8;
+    if (grid > Q.B)
+        grid = Q.B;
+    // as in pbp_decode: early stop without freezing runs the freezing kernel
+    // with the walk switched off
+    if (Q.early_stop)
+        hipLaunchKernelGGL((quant_r10_kernel<true, true>), dim3(grid), dim3(64), 0, st, P);
+    else if (Q.freezing)
+        hipLaunchKernelGGL((quant_r10_kernel<true, false>), dim3(grid), dim3(64), 0, st, P);
+    else
+        hipLaunchKernelGGL((quant_r10_kernel<false, false>), dim3(grid), dim3(64), 0, st, P);
+    return hipGetLastError();
+}
+
 }  // namespace
 
 extern "C" int32_t pbp_decode_quant(const pbp_code *code, const float *llr,
@@ -325,6 +389,19 @@ extern "C" int32_t pbp_decode_quant(const pbp_code *code, const float *llr,
     P.pe_out = pe_out;
     P.soft_out = soft_out;
     hipStream_t st = (hipStream_t)stream;
+    if (code->m == pbp::r10::M) {
+        pbp::Workspace ws;
+        const int32_t rc = pbp::stream_workspace(code, st, &ws);
+        if (rc != PBP_OK)
+            return rc;
+        const hipError_t e = launch_quant_r10(code, P, (float)P.a16 / 16.0f,
+                                              ws.counter, st);
+        return e == hipSuccess ? PBP_OK : PBP_EDEVICE;
+    }
+    // the LDS path keeps messages as bytes: a scaled minimum must fit
+    // (8-bit messages with alpha above 1 can reach 246)
+    if ((P.a16 * P.Q + 8) >> 4 > 127)
+        return PBP_EUNSUPPORTED;
     hipError_t e;
     switch (code->m) {
     case 1: e = launch_quant<1>(code, P, st); break;
@@ -336,7 +413,6 @@ extern "C" int32_t pbp_decode_quant(const pbp_code *code, const float *llr,
     case 7: e = launch_quant<7>(code, P, st); break;
     case 8: e = launch_quant<8>(code, P, st); break;
     case 9: e = launch_quant<9>(code, P, st); break;
-    case 10: e = launch_quant<10>(code, P, st); break;
     case 11: e = launch_quant<11>(code, P, st); break;
     case 12: e = launch_quant<12>(code, P, st); break;
     default: return PBP_EUNSUPPORTED;

@@ -102,6 +102,73 @@ struct Params {
     int32_t *iters_out;
     int64_t *pe_out;
     float *soft_out;
+    // fixed-point messages only
+    float qmax;            // Q = 2^(b-1) - 1
+    int32_t frac;          // fraction bits of the channel quantizer
+    int8_t *soft_q;        // B x N or null: sat(R + L) at column M+1
+};
+
+// Message arithmetic.  ArithF32 is eq. (1) in FP32 min-sum.  ArithFixed runs
+// the same decoder on saturating b-bit integers (Sections I and V: the
+// hardware setting in which the paper counts a PE): every message is an
+// integer in [-Q, Q], held exactly in an FP32 register (all sums, products
+// and thresholds stay far below 2^24), the +-inf of frozen rows become +-Q,
+// and hard decisions keep the exact sum's sign.
+struct ArithF32 {
+    static constexpr bool kFixed = false;
+    __device__ static __forceinline__ float big(const Params &) { return kInf; }
+    __device__ static __forceinline__ float channel(float v, const Params &) { return v; }
+    __device__ static __forceinline__ void pe(float La, float Lb, float Ra, float Rb,
+                                              const Params &P, float &la, float &lbv,
+                                              float &ra, float &rb)
+    {
+        const float alpha = P.alpha;
+        const float s = Lb + Rb;
+        const float aLa = salpha(La, alpha);
+        const float g1 = aLa * clampm(La, Ra);
+        la = aLa * clampm(La, s);
+        lbv = Lb + g1;
+        ra = salpha(Ra, alpha) * clampm(Ra, s);
+        rb = Rb + g1;
+    }
+};
+
+struct ArithFixed {
+    static constexpr bool kFixed = true;
+    __device__ static __forceinline__ float big(const Params &P) { return P.qmax; }
+    __device__ static __forceinline__ float sat(float v, float q)
+    {
+        return __builtin_amdgcn_fmed3f(v, -q, q);
+    }
+    // channel: clamp(round(LLR 2^F), -Q, Q), halves away from zero (the
+    // product by 2^F is exact)
+    __device__ static __forceinline__ float channel(float v, const Params &P)
+    {
+        return sat(roundf(ldexpf(v, P.frac)), P.qmax);
+    }
+    // sign(x) sign(y) floor((a min(|x|, |y|) + 8) / 16), a = round(16 alpha):
+    // t = (a/16) sign(x) clampm(x, y) is a multiple of 1/16 computed exactly,
+    // and trunc(t + copysign(1/2, t)) = sign(t) floor(|t| + 1/2)
+    __device__ static __forceinline__ float term(float sa, float x, float y)
+    {
+        const float t = sa * clampm(x, y);
+        return truncf(t + __builtin_copysignf(0.5f, t));
+    }
+    // one PE of eq. (1): every sum saturates, the scaled minima do not
+    __device__ static __forceinline__ void pe(float La, float Lb, float Ra, float Rb,
+                                              const Params &P, float &la, float &lbv,
+                                              float &ra, float &rb)
+    {
+        const float a = P.alpha;           // round(16 alpha) / 16, exact
+        const float q = P.qmax;
+        const float s = sat(Lb + Rb, q);
+        const float aLa = salpha(La, a);
+        const float g1 = term(aLa, La, Ra);
+        la = term(aLa, La, s);
+        lbv = sat(Lb + g1, q);
+        ra = term(salpha(Ra, a), Ra, s);
+        rb = sat(Rb + g1, q);
+    }
 };
 
 // LDS per wavefront
@@ -147,7 +214,7 @@ __host__ __device__ constexpr int swz_lane_bits(int mp)
     return m;
 }
 
-template <bool FRZ, bool ES>
+template <bool FRZ, bool ES, class Ar = ArithF32>
 struct Decoder {
     const Params &P;
     Smem &S;
@@ -247,14 +314,15 @@ struct Decoder {
     // still be read, so only those consult the kept decisions.
     __device__ __forceinline__ float l11(int q, int lo, int hi) const
     {
-        float v = fzbit(MA, q) ? kInf : 0.0f;
+        const float big = Ar::big(P);
+        float v = fzbit(MA, q) ? big : 0.0f;
         if (FRZ) {
             const int rq = rowq(MA, q);
             if (rq + 252 >= lo && rq < hi) {
                 // row >= lo and row < hi, compared as the lane part against
                 // uniform bounds (no per-register row value stays live)
                 if (lr[MA] >= opaque_s(lo - rq) && lr[MA] < opaque_s(hi - rq))
-                    v = S.dec[row<MA>(q)] ? -kInf : kInf;
+                    v = S.dec[row<MA>(q)] ? -big : big;
             }
         }
         return v;
@@ -283,15 +351,15 @@ struct Decoder {
 #pragma unroll
             for (int qh = 0; qh < 4; qh++) {
                 const float4 v = *reinterpret_cast<const float4 *>(src + qh * 256 + lane * 4);
-                ch[qh * 4 + 0] = v.x;
-                ch[qh * 4 + 1] = v.y;
-                ch[qh * 4 + 2] = v.z;
-                ch[qh * 4 + 3] = v.w;
+                ch[qh * 4 + 0] = Ar::channel(v.x, P);
+                ch[qh * 4 + 1] = Ar::channel(v.y, P);
+                ch[qh * 4 + 2] = Ar::channel(v.z, P);
+                ch[qh * 4 + 3] = Ar::channel(v.w, P);
             }
         } else {
 #pragma unroll
             for (int q = 0; q < Q; q++)
-                ch[q] = src[(q >> 2) * 256 + lane * 4 + (q & 3)];
+                ch[q] = Ar::channel(src[(q >> 2) * 256 + lane * 4 + (q & 3)], P);
         }
     }
 
@@ -343,7 +411,6 @@ struct Decoder {
     {
         constexpr int MP = smap(J);
         constexpr int QB = QA | (1 << sqb(J));
-        const float alpha = P.alpha;
         float La, Lb;
         if constexpr (J == M) {
             La = KEPT ? l11(QA, l11lo, l11hi) : l11(QA, 0, 0);
@@ -355,13 +422,10 @@ struct Decoder {
         }
         const float Ra = (J == 1) ? ch[QA] : R[QA];
         const float Rb = (J == 1) ? ch[QB] : R[QB];
-        const float s = Lb + Rb;
-        const float aLa = salpha(La, alpha);
-        const float g1 = aLa * clampm(La, Ra);
-        const float la = aLa * clampm(La, s);
-        const float lbv = Lb + g1;
-        R[QA] = salpha(Ra, alpha) * clampm(Ra, s);
-        R[QB] = Rb + g1;
+        float la, lbv, ra, rb;
+        Ar::pe(La, Lb, Ra, Rb, P, la, lbv, ra, rb);
+        R[QA] = ra;
+        R[QB] = rb;
         if constexpr (J == 1) {
             if constexpr (ES) {
                 X[QA] = ballot(Ra + la < 0.0f);
@@ -612,7 +676,7 @@ struct Decoder {
                     S.dec[lr[MP] + rq] = (uint8_t)(lane_fx(W[i]) & 1u);
                     if constexpr (lbcol(J + 1) >= 0)
                         S.lb[lbcol(J + 1)][sl[MP] ^ swz(rq)] =
-                            ((X0[i] >> lane) & 1) ? -kInf : kInf;
+                            ((X0[i] >> lane) & 1) ? -Ar::big(P) : Ar::big(P);
                 }
             }
         }
@@ -633,7 +697,7 @@ struct Decoder {
             for (int q = 0; q < Q; q++) {
                 const int rq = rowq(MP, q);
                 if (rq + lanemax(MP) >= lo && rq < hi) {
-                    const float fixed = check_input<J>(q) < 0.0f ? -kInf : kInf;
+                    const float fixed = check_input<J>(q) < 0.0f ? -Ar::big(P) : Ar::big(P);
                     Ln[q] = (lr[MP] >= opaque_s(lo - rq) && lr[MP] < opaque_s(hi - rq))
                                 ? fixed : Ln[q];
                 }
@@ -809,7 +873,24 @@ struct Decoder {
         uint8_t *out = P.info_out + frame * P.K;
         for (int k = lane; k < P.K; k += 64)
             out[k] = S.dec[P.info_pos[k]];
-        if (P.soft_out) {
+        if constexpr (Ar::kFixed) {
+            if (P.soft_q) {
+                // sat(R + L) at column M+1 (+-Q at frozen CSFG rows), as bytes
+                const float q = P.qmax;
+                int8_t *so = P.soft_q + frame * N;
+#pragma unroll
+                for (int qh = 0; qh < 4; qh++) {
+#pragma unroll
+                    for (int ql = 0; ql < 4; ql++) {
+                        const int qq = qh * 4 + ql;
+                        const int r = row<MA>(qq);
+                        const float v = r < fm ? (S.dec[r] ? -q : q)
+                                               : Ar::sat(R[qq] + l11(qq, 0, 0), q);
+                        so[qh * 256 + lane * 4 + ql] = (int8_t)(int)v;
+                    }
+                }
+            }
+        } else if (P.soft_out) {
             float *so = P.soft_out + frame * N;
 #pragma unroll
             for (int qh = 0; qh < 4; qh++) {

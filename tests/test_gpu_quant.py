@@ -96,3 +96,62 @@ def test_quant_rejects(env):
     with pytest.raises(pbp.PbpError):
         pbp.pbp_decode_quant(code, torch.zeros((1, 64), device="cuda"),
                              bits=9)
+
+
+def test_quant_alpha_above_one(env):
+    """alpha = 1.25 (a = 20) with 8-bit messages: a scaled minimum reaches
+    (20 * 127 + 8) >> 4 = 159 > Q.  The oracle keeps it unsaturated, and the
+    N = 1024 register decoder holds it exactly; the byte-LDS kernel of the
+    other lengths cannot, and rejects the format."""
+    pbp, torch = env
+    N, K = 1024, 512
+    fz = frozen_mask(N, K)
+    _, _, llr = make_frames(N, K, 40, 2.5, stream=1400)
+    code = pbp.Code(N, K, fz)
+    for mode in ("plain", "es_frz"):
+        o = dict(freeze_input=1, freeze_walk=0, alpha=1.25)
+        o.update(MODES[mode])
+        got = pbp.pbp_decode_quant(code, torch.from_numpy(llr).cuda(), bits=8,
+                                   frac=3, soft=True, **o)
+        ref = oracle.decode_quant(llr, fz, bits=8, frac=3, soft=True, **o)
+        assert np.array_equal(got["info"].cpu().numpy(), ref["info"])
+        assert np.array_equal(got["iters"].cpu().numpy(), ref["iters"])
+        assert np.array_equal(got["pe"].cpu().numpy(), ref["pe"])
+        assert np.array_equal(got["soft"].cpu().numpy().astype(np.int32),
+                              ref["soft"])
+    short = pbp.Code(64, 32, frozen_mask(64, 32))
+    with pytest.raises(pbp.PbpError):
+        pbp.pbp_decode_quant(short, torch.zeros((1, 64), device="cuda"),
+                             bits=8, alpha=1.25)
+    # 7-bit messages fit a byte at any alpha below 2
+    pbp.pbp_decode_quant(short, torch.zeros((1, 64), device="cuda"), bits=7,
+                         alpha=1.25)
+
+
+def test_quant_unaligned_and_many_frames(env):
+    """N = 1024: LLR rows that are not 16-byte aligned (scalar loads), and a
+    batch of more frames than resident wavefronts, so each wavefront takes
+    several frames from the stream's counter; a second call on the same
+    stream starts from a rewound counter."""
+    pbp, torch = env
+    N, K = 1024, 512
+    fz = frozen_mask(N, K)
+    code = pbp.Code(N, K, fz)
+    _, _, llr = make_frames(N, K, 64, 3.0, stream=1500)
+    buf = torch.zeros(64 * N + 1, device="cuda")
+    buf[1:] = torch.from_numpy(llr).cuda().reshape(-1)
+    o = dict(MODES["es_frz"], freeze_input=1, freeze_walk=0)
+    got = pbp.pbp_decode_quant(code, buf[1:].view(64, N), bits=8, frac=3, **o)
+    ref = oracle.decode_quant(llr, fz, bits=8, frac=3, **o)
+    assert np.array_equal(got["info"].cpu().numpy(), ref["info"])
+    assert np.array_equal(got["iters"].cpu().numpy(), ref["iters"])
+    assert np.array_equal(got["pe"].cpu().numpy(), ref["pe"])
+    B = 20000
+    rep = np.tile(llr, (B // 64 + 1, 1))[:B]
+    d = torch.from_numpy(rep).cuda()
+    for _ in range(2):
+        got = pbp.pbp_decode_quant(code, d, bits=8, frac=3, **o)
+        idx = np.arange(B) % 64
+        assert np.array_equal(got["info"].cpu().numpy(), ref["info"][idx])
+        assert np.array_equal(got["iters"].cpu().numpy(), ref["iters"][idx])
+        assert np.array_equal(got["pe"].cpu().numpy(), ref["pe"][idx])
