@@ -24,12 +24,16 @@
 // The schedule, the PE arithmetic (pe_eq1), the CSFG walk and the stop test
 // are those of the generic decoder, so results agree bit for bit.  LDS: the
 // odd columns ((m-1)/2 columns of N floats), two R columns and two columns
-// of check inputs used in turn, and four bit words per 64 rows (one of them
-// the frozen mask): 146.1 KB at N = 4096, 73.1 KB at N = 2048.  The channel
-// LLRs stay in registers.  A pair of stages costs one barrier.  The first
-// test of each check runs on the one wavefront that holds the tested word in
-// registers, before that barrier; only a check that passes it (rare) runs
-// the walk on the whole group.
+// of check inputs used in turn, four bit words per 64 rows (one of them the
+// frozen mask) and the published check words: 147.0 KB at N = 4096, 73.5 KB
+// at N = 2048.  The channel
+// LLRs stay in registers.  A pair of stages costs one barrier.  Checks of
+// small blocks (at most 64 rows) run their test on the one wavefront that
+// holds the block's word in registers, before that barrier; only a check that
+// passes it runs the walk on the whole group.  Checks of large blocks are
+// published: each wavefront ballots its words of the block before the
+// barrier, and every wavefront transforms and tests them after it, so a
+// failed check costs no further barrier.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -50,6 +54,7 @@ using generic::kBatch;
 using generic::kInf;
 using generic::kMaxWordsPerLane;
 using generic::pe_eq1;
+using generic::shfl_xor64;
 
 template <int M>
 struct Shape {
@@ -61,12 +66,15 @@ struct Shape {
 };
 
 // LDS bytes of one decoder: [u64 xw NW][u64 dw NW][u64 cw NW][u64 fw NW]
-// [Ctl][int first-test flags 2 x 2][f32 R, two columns of N, and the walk's check inputs, two columns
-// of N][f32 L at the odd columns, NL x N]
+// [u64 published check words, 2 (pair parity) x 2 (stage of the pair) x
+// N/128][Ctl][int first-test flags 2 x 2][f32 R, two columns of N, and the
+// walk's check inputs, two columns of N][f32 L at the odd columns, NL x N]
 template <int M>
 __host__ __device__ constexpr size_t lds_bytes()
 {
-    return 4 * sizeof(uint64_t) * Shape<M>::NW + sizeof(Ctl) + 4 * sizeof(int) +
+    return 4 * sizeof(uint64_t) * Shape<M>::NW +
+           4 * sizeof(uint64_t) * (Shape<M>::N / 128) + sizeof(Ctl) +
+           4 * sizeof(int) +
            sizeof(float) * (size_t)(4 + Shape<M>::NL) * Shape<M>::N;
 }
 
@@ -86,6 +94,7 @@ struct Decoder {
     uint64_t *dw;         // kept source decisions of frozen rows
     uint64_t *cw;         // channel-side decisions of the stop test
     uint64_t *fw;         // the frozen mask (bit i of word i >> 6)
+    uint64_t *xp;         // published check words (see run_pair)
     Ctl *ctl;
     int *fl;              // first-test results, [pair parity][stage of pair]
     float *Rb;            // two R columns used in turn by the pairs, and the
@@ -107,7 +116,8 @@ struct Decoder {
         dw = xw + NW;
         cw = dw + NW;
         fw = cw + NW;
-        ctl = reinterpret_cast<Ctl *>(fw + NW);
+        xp = fw + NW;
+        ctl = reinterpret_cast<Ctl *>(xp + 4 * (N / 128));
         fl = reinterpret_cast<int *>(ctl + 1);
         Rb = reinterpret_cast<float *>(fl + 4);
         Lo = Rb + 4 * N;
@@ -314,6 +324,65 @@ struct Decoder {
             *flag = (ffx_word(word) & fz) == 0;
     }
 
+    // Published checks.  Where a check's block is made of whole 64-row words
+    // and each word is one register of one wavefront (pair row bit SB >= 6),
+    // every wavefront ballots its words of the block before the pair's
+    // barrier into buf, and after it every wavefront transforms all of the
+    // block's words (at most N/128: one per lane) and tests eq. (4) alike.
+    // A failed check, the common case for large blocks, then costs no
+    // barrier and no shared write.  (The first test on the block's last word
+    // is no filter there: a large block's last rows are mostly information
+    // rows, so that word nearly always passes.)
+    //
+    // publish: the words of CSFG pj (2^LB rows) held by this wavefront
+    template <int LB>
+    __device__ __forceinline__ void publish(int pj, const float (&v)[4],
+                                            const int (&rows)[4], uint64_t *buf) const
+    {
+        constexpr int NB = 1 << (LB - 6);
+        const int w0 = pj << (LB - 6);
+#pragma unroll
+        for (int k = 0; k < 4; k++) {
+            // the wavefront's 64 rows of register k are one aligned word
+            const int o = (__builtin_amdgcn_readfirstlane(rows[k]) >> 6) - w0;
+            if (o >= 0 && o < NB) {
+                const uint64_t b = __ballot(v[k] < 0.0f);
+                if (lane == 0)
+                    buf[o] = b;
+            }
+        }
+    }
+
+    // eqs. (3)-(4) on the published words of CSFG pj: true when it passes;
+    // u: this lane's transformed word (lane w, word w of the block)
+    template <int LB>
+    __device__ __forceinline__ bool published_check(int pj, const uint64_t *buf,
+                                                    uint64_t &u) const
+    {
+        constexpr int NB = 1 << (LB - 6);
+        const int w0 = pj << (LB - 6);
+        const bool in = lane < NB;
+        uint64_t x = in ? ffx_word(buf[lane]) : 0;
+#pragma unroll
+        for (int L = 1; L < NB; L <<= 1) {
+            const uint64_t o = shfl_xor64(x, L);
+            if (!(lane & L))
+                x ^= o;
+        }
+        u = x;
+        return !__any(in && (x & fw[w0 + (in ? lane : 0)]) != 0);
+    }
+
+    // after a published check of CSFG pj passed: the CSFG's decisions replace
+    // those of any sub-CSFG frozen before it (wavefront 0 writes them)
+    template <int LB>
+    __device__ __forceinline__ void keep_published(int pj, uint64_t u) const
+    {
+        constexpr int NB = 1 << (LB - 6);
+        if (wv == 0 && lane < NB)
+            dw[(pj << (LB - 6)) + lane] = u;
+    }
+
     // One pair of stages: J = 2 PI + 1 and J + 1, with one barrier.
     //  - R at column J comes from the channel (PI = 0) or the R column the
     //    previous pair wrote; R at column J+2 goes to the other R column,
@@ -419,15 +488,27 @@ struct Decoder {
         // first tests of both walks, stage J+1's assuming stage J freezes
         // nothing (else its walk runs in full below)
         int *flags = fl + 2 * (PI & 1);
+        // published words, by pair parity: stage J's block, then stage J+1's
+        uint64_t *xpJ = xp + (PI & 1) * (2 * (N / 128));
+        uint64_t *xpJ1 = xpJ + N / 128;
+        constexpr bool PUBJ = SB >= 6, PUB1 = SB >= 7;
         const int pj1s = P.freezing ? max(p[J + 1], 2 * pj0) : 0;
-        if (walkJ)
-            owner_test<SB, true>(pj0, vv, flags);
-        if (P.freezing && pj1s < (1 << (J + 1))) {
+        if (walkJ) {
+            if constexpr (PUBJ)
+                publish<SB + 1>(pj0, vv, rows, xpJ);
+            else
+                owner_test<SB, true>(pj0, vv, flags);
+        }
+        if (P.freezing && pj1s < (1 << (J + 1)) &&
+            (P.freeze_walk != 0 || walking)) {
             float v1[4];
 #pragma unroll
             for (int k = 0; k < 4; k++)
                 v1[k] = P.freeze_input ? Rv[k] + Lin[k] : Rv[k];
-            owner_test<SB, false>(pj1s, v1, flags + 1);
+            if constexpr (PUB1)
+                publish<SB>(pj1s, v1, rows, xpJ1);
+            else
+                owner_test<SB, false>(pj1s, v1, flags + 1);
         }
         // R at column J+2 and the walk's inputs, in row order; then the
         // barrier; then stage J's L outputs
@@ -449,39 +530,100 @@ struct Decoder {
         }
 
         // ---- walk at stage J: column J+1 is held in registers ----
-        if (walkJ && flags[0]) {
-            auto vin = [&](int i) { return Vb[i]; };
-            walk<J>(pj0, vin, [](int, bool) {});
+        auto vinJ = [&](int i) { return Vb[i]; };
+        bool ranJ = false;
+        if constexpr (PUBJ) {
+            p[J] = pj0;
+            uint64_t u;
+            if (walkJ && published_check<SB + 1>(pj0, xpJ, u)) {
+                keep_published<SB + 1>(pj0, u);
+                p[J] = pj0 + 1;
+                if (P.freeze_walk == 0)
+                    walking = 0;
+                // the kept decisions before any reader
+                __syncthreads();
+                if (P.freeze_walk == 2)
+                    walk<J>(pj0 + 1, vinJ, [](int, bool) {});
+                ranJ = true;
+            }
+        } else {
+            if (walkJ && flags[0]) {
+                walk<J>(pj0, vinJ, [](int, bool) {});
+                ranJ = true;
+            } else {
+                p[J] = pj0;
+            }
+        }
+        if (ranJ) {
             const int lo = pj0 << (M - J), hi = p[J] << (M - J);
 #pragma unroll
             for (int k = 0; k < 4; k++)
                 if (rows[k] >= lo && rows[k] < hi)
                     Lr[PI][k] = vv[k] < 0.0f ? -kInf : kInf;
-        } else {
-            p[J] = pj0;
         }
         pe += (N - (p[J] << (M - J))) >> 1;
 
         // ---- walk at stage J+1: column J+2 is in LDS, or the prior ----
-        // (skipped when its first test failed on the blocks assumed above)
-        if (P.freezing &&
-            (p[J] != pj0 || pj1s >= (1 << (J + 1)) || flags[1])) {
-            const int pj1 = max(p[J + 1], 2 * p[J]);
-            if constexpr (J + 2 <= M) {
-                float *Lc = lcol(J + 2);
-                auto vin = [&](int i) {
-                    return P.freeze_input ? Rout[i] + Lc[i] : Rout[i];
-                };
-                walk<J + 1>(pj1, vin,
-                            [&](int i, bool x) { Lc[i] = x ? -kInf : kInf; });
-            } else {
-                auto vin = [&](int i) {
-                    return P.freeze_input ? Rout[i] + prior(i) : Rout[i];
-                };
-                walk<J + 1>(pj1, vin, [](int, bool) {});
+        // (skipped when its first test failed on the blocks assumed above;
+        // with large blocks, the published check when stage J froze nothing)
+        bool done1 = false;
+        if constexpr (PUB1) {
+            if (P.freezing && p[J] == pj0) {
+                done1 = true;
+                p[J + 1] = pj1s;
+                uint64_t u;
+                if (pj1s < (1 << (J + 1)) && (P.freeze_walk != 0 || walking) &&
+                    published_check<SB>(pj1s, xpJ1, u)) {
+                    keep_published<SB>(pj1s, u);
+                    // L at column J+2 := (-1)^xhat inf on the block's rows
+                    if constexpr (J + 2 <= M) {
+                        float *Lc = lcol(J + 2);
+                        const int r0 = pj1s << SB;
+                        for (int i = tid; i < (1 << SB); i += NT)
+                            Lc[r0 + i] = ((xpJ1[i >> 6] >> (i & 63)) & 1) ? -kInf : kInf;
+                    }
+                    p[J + 1] = pj1s + 1;
+                    if (P.freeze_walk == 0)
+                        walking = 0;
+                    __syncthreads();
+                    if (P.freeze_walk == 2) {
+                        if constexpr (J + 2 <= M) {
+                            float *Lc = lcol(J + 2);
+                            auto vin = [&](int i) {
+                                return P.freeze_input ? Rout[i] + Lc[i] : Rout[i];
+                            };
+                            walk<J + 1>(pj1s + 1, vin,
+                                        [&](int i, bool x) { Lc[i] = x ? -kInf : kInf; });
+                        } else {
+                            auto vin = [&](int i) {
+                                return P.freeze_input ? Rout[i] + prior(i) : Rout[i];
+                            };
+                            walk<J + 1>(pj1s + 1, vin, [](int, bool) {});
+                        }
+                    }
+                }
             }
-        } else if (P.freezing) {
-            p[J + 1] = pj1s;
+        }
+        if (!done1) {
+            if (P.freezing &&
+                (p[J] != pj0 || pj1s >= (1 << (J + 1)) || flags[1] || PUB1)) {
+                const int pj1 = max(p[J + 1], 2 * p[J]);
+                if constexpr (J + 2 <= M) {
+                    float *Lc = lcol(J + 2);
+                    auto vin = [&](int i) {
+                        return P.freeze_input ? Rout[i] + Lc[i] : Rout[i];
+                    };
+                    walk<J + 1>(pj1, vin,
+                                [&](int i, bool x) { Lc[i] = x ? -kInf : kInf; });
+                } else {
+                    auto vin = [&](int i) {
+                        return P.freeze_input ? Rout[i] + prior(i) : Rout[i];
+                    };
+                    walk<J + 1>(pj1, vin, [](int, bool) {});
+                }
+            } else if (P.freezing) {
+                p[J + 1] = pj1s;
+            }
         }
     }
 
