@@ -702,7 +702,7 @@ def bench_c1(args, pbp, torch):
         pe_per_frame=round(float(pe.mean()), 1), fer=errs / B,
         ms_per_step_median=round(med, 4), end_to_end_ms=round(e2e, 3),
         parity=parity,
-        roofline=_alu_roofline(achieved, "c1", "bp_decode_kernel<6, false>",
+        roofline=_alu_roofline(achieved, "c1", "bp_decode_wave_kernel<6>",
                                B, ms, "12 operations per PE activation"))
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(llr, K, out["info"], opts,
@@ -1036,16 +1036,19 @@ def bench_round_trip(args, pbp, torch):
     base = dict(early_stop=True, freezing=False, max_iter=max_iter,
                 alpha=alpha)
     res = {}
-    for name, sched in (("round_trip", "round_trip"), ("single", "single")):
+    for name, sched, es in (("round_trip", "round_trip", True),
+                            ("single", "single", True),
+                            ("plain40", "single", False)):
         ms, _, out, med, _ = time_mode(pbp, torch, code, d_llr,
-                                       dict(base, schedule=sched),
+                                       dict(base, schedule=sched,
+                                            early_stop=es),
                                        args.steps, args.warmup)
         errs = int(np.sum(np.any(out["info"] != info, axis=1)))
         res[name] = dict(ms=ms, median=med, errors=errs, fer=errs / B,
                          iters=float(out["iters"].mean()),
                          pe=float(out["pe"].mean()),
                          mbps=B * K / (ms / 1e3) / 1e6, info=out["info"])
-    r, s1 = res["round_trip"], res["single"]
+    r, s1, p40 = res["round_trip"], res["single"], res["plain40"]
     achieved = OPS_PER_PE_PASS * r["pe"] * B / (r["ms"] / 1e3) / 1e12
     line = _line(
         "decoded info Mbit/s at N=1024 R=1/2 3.0dB, round-trip BP schedule "
@@ -1064,6 +1067,15 @@ def bench_round_trip(args, pbp, torch):
             "fer_ci95": list(wilson(s1["errors"], B, 1.959963984540054)),
             "avg_iters": round(s1["iters"], 3),
             "pe_per_frame": round(s1["pe"], 1)},
+        plain40={
+            "mbps": round(p40["mbps"], 2), "ms_per_step": round(p40["ms"], 4),
+            "fer": p40["fer"],
+            "fer_ci95": list(wilson(p40["errors"], B, 1.959963984540054)),
+            "avg_iters": round(p40["iters"], 3),
+            "pe_per_frame": round(p40["pe"], 1)},
+        # context only: the round trip has no freezing, so this is not the
+        # freezing decoder's speed-up (that is the headline line's)
+        speedup_vs_plain40_context=round(r["mbps"] / p40["mbps"], 3),
         roofline=_alu_roofline(achieved, "round_trip",
                                "bp_round_trip_kernel<10>", B, r["ms"],
                                "8 operations per PE activation of one pass, "

@@ -128,6 +128,93 @@ hipError_t launch_decode(const pbp_code *c, DecodeParams &P, float *state,
     return hipGetLastError();
 }
 
+// N <= 64 without freezing: one wavefront per frame, row i on lane i, every
+// message in registers.  Stage j pairs lanes i and i ^ h (h = N / 2^j): each
+// lane reads its partner's L (column j+1) and R (column j) across lanes,
+// evaluates eq. (1) as the other kernels do, and keeps its own row's two
+// outputs, so a sweep needs neither LDS nor barriers.  The stop test is one
+// ballot word: lane i's bit of u F^{(x)m} is the parity of u over the lanes
+// whose index contains i.  With freezing, frames take the generic decoder.
+template <int M>
+__global__ __launch_bounds__(64) void bp_decode_wave_kernel(DecodeParams P)
+{
+    constexpr int N = 1 << M;
+    static_assert(M >= 1 && M <= 6, "one row per lane");
+    const int lane = (int)__builtin_amdgcn_workitem_id_x();
+    const bool act = lane < N;
+    const bool frz = act && ((P.frozen_words[0] >> lane) & 1);
+    // lanes whose index contains this lane's index bits
+    uint64_t sup = ~0ull;
+#pragma unroll
+    for (int lb = 0; lb < 6; lb++)
+        if ((lane >> lb) & 1)
+            sup &= (lb == 0 ? 0xAAAAAAAAAAAAAAAAull : lb == 1 ? 0xCCCCCCCCCCCCCCCCull
+                    : lb == 2 ? 0xF0F0F0F0F0F0F0F0ull : lb == 3 ? 0xFF00FF00FF00FF00ull
+                    : lb == 4 ? 0xFFFF0000FFFF0000ull : 0xFFFFFFFF00000000ull);
+    const float prior = frz ? kInf : 0.0f;     // L at column m+1
+    const float alpha = P.alpha;
+    for (int64_t frame = blockIdx.x; frame < P.B; frame += gridDim.x) {
+        const float ch = act ? P.llr[frame * N + lane] : 0.0f;
+        float L[M];                            // L at columns 1..m
+#pragma unroll
+        for (int c = 0; c < M; c++)
+            L[c] = 0.0f;
+        float R = 0.0f;                        // R at column m+1 after a sweep
+        int t = 1;
+        for (; t <= P.max_iter; t++) {
+            R = ch;
+            uint64_t xw = 0;
+#pragma unroll
+            for (int j = 1; j <= M; j++) {
+                const int h = N >> j;
+                const float Lin = j == M ? prior : L[j];
+                const float Lp = __shfl_xor(Lin, h, 64);
+                const float Rp = __shfl_xor(R, h, 64);
+                const bool up = (lane & h) != 0;
+                float oLa, oLb, oRa, oRb;
+                pe_eq1(up ? Lp : Lin, up ? Lin : Lp, up ? Rp : R, up ? R : Rp,
+                       alpha, oLa, oLb, oRa, oRb);
+                L[j - 1] = up ? oLb : oLa;
+                // channel-side decisions of the stop test: R + L at column 1
+                if (j == 1 && P.early_stop)
+                    xw = __ballot(act && R + L[0] < 0.0f);
+                R = up ? oRb : oRa;
+            }
+            if (P.early_stop) {
+                const uint64_t u = __ballot(act && !frz && R < 0.0f);
+                const uint32_t par = (uint32_t)(__builtin_popcount((uint32_t)(u & sup)) +
+                                                __builtin_popcount((uint32_t)((u & sup) >> 32))) & 1u;
+                if (__ballot(act && par != (uint32_t)((xw >> lane) & 1)) == 0)
+                    break;
+            }
+        }
+        if (t > P.max_iter)
+            t = P.max_iter;
+        const uint64_t dec = __ballot(act && R < 0.0f);
+        uint8_t *out = P.info_out + frame * P.K;
+        if (lane < P.K)
+            out[lane] = (uint8_t)((dec >> P.info_pos[lane]) & 1);
+        if (P.soft_out && act)
+            P.soft_out[frame * N + lane] = R + prior;
+        if (lane == 0) {
+            P.iters_out[frame] = t;
+            if (P.pe_out)
+                P.pe_out[frame] = (int64_t)t * (M * N / 2);
+        }
+    }
+}
+
+template <int M>
+hipError_t launch_wave(DecodeParams &P, hipStream_t st)
+{
+    int64_t grid = P.B;
+    if (grid > (1ll << 30))
+        grid = 1ll << 30;
+    hipLaunchKernelGGL(bp_decode_wave_kernel<M>, dim3((unsigned)grid), dim3(64), 0,
+                       st, P);
+    return hipGetLastError();
+}
+
 // counter: the frame counter pair (zero), or null for a grid-stride launch
 template <int M>
 hipError_t launch_pair(const pbp_code *c, DecodeParams &P, int *counter,
@@ -231,6 +318,18 @@ int32_t decode_impl(const pbp_code *code, const float *llr, int64_t B,
     if (code->m == pbp::r10::M && code->d_fzw10 && B <= (int64_t(1) << 30)) {
         e = pbp::r10::launch(code, llr, B, opts, info_out, iters_out, pe_out,
                              soft_out, sc->counter, st);
+        return e == hipSuccess ? PBP_OK : PBP_EDEVICE;
+    }
+    // codes up to 64 without freezing: one wavefront per frame in registers
+    if (code->m <= 6 && !opts->freezing) {
+        switch (code->m) {
+        case 1: e = launch_wave<1>(P, st); break;
+        case 2: e = launch_wave<2>(P, st); break;
+        case 3: e = launch_wave<3>(P, st); break;
+        case 4: e = launch_wave<4>(P, st); break;
+        case 5: e = launch_wave<5>(P, st); break;
+        default: e = launch_wave<6>(P, st); break;
+        }
         return e == hipSuccess ? PBP_OK : PBP_EDEVICE;
     }
     switch (code->m) {

@@ -67,6 +67,8 @@ CASES = [
     # N, K, Eb/N0, frames
     (2, 1, 1.0, 64),
     (8, 4, 2.0, 200),
+    (16, 8, 2.0, 200),
+    (32, 11, 2.0, 200),
     (64, 32, 2.5, 400),
     (128, 64, 2.0, 200),
     (256, 85, 2.0, 100),
@@ -361,3 +363,17 @@ def test_one_handle_on_two_streams(env, N, K, B):
     torch.cuda.synchronize()
     for k in ref1:
         assert torch.equal(o1[k], ref1[k]), k
+
+
+def test_small_code_many_frames(env):
+    """N = 64 without freezing runs one wavefront per frame in registers:
+    a batch of 20000 frames (more wavefronts than the chip holds at once),
+    both stop rules, every frame against the oracle, posteriors included."""
+    N, K, B = 64, 32, 20000
+    fz = frozen_mask(N, K)
+    _, _, llr = make_frames(N, K, B, 2.5, stream=2600)
+    for mode in ("plain", "es"):
+        print(f"[decode] small code, {B} frames, mode={mode}", flush=True)
+        r = oracle.decode(llr, fz, max_iter=40, soft=True, **MODES[mode])
+        g = gpu_decode(env, N, K, llr, max_iter=40, **MODES[mode])
+        assert_parity(g, r, K, fz)
