@@ -127,9 +127,11 @@ int32_t pbp_encode(const pbp_code *code, const uint8_t *info, int64_t B,
  *             computation count), or NULL
  *   soft_out  device, B x N FP32, or NULL: the posterior LLR of each source
  *             bit at exit (R + L at column m+1; +-inf inside frozen CSFGs)
- * Codes up to N = 4096 keep every message on chip (N = 1024: one wavefront
- * per frame, registers and LDS; N = 2048, 4096: one workgroup of N/4
- * threads per frame, half the L columns in VGPRs, the rest in LDS).  Longer
+ * Codes up to N = 4096 keep every message on chip (N <= 64: one wavefront
+ * per frame, a row per lane, registers only; N = 128..512: one workgroup per
+ * frame in LDS; N = 1024: one wavefront per frame, registers and LDS;
+ * N = 2048, 4096: one workgroup of N/4 threads per frame, half the L
+ * columns in VGPRs, the rest in LDS).  Longer
  * codes keep L in device memory.  The frame counter of the persistent
  * kernels and the message state of codes longer than 4096 come from the
  * stream's workspace (see the conventions above), so calls on different
