@@ -51,7 +51,8 @@ def _csrc(*names):
 
 TRAFFIC_RECORDS = {
     "n1024": ("traffic_bp_decode_r10_n1024_3db.txt",
-              _csrc("pbp_r10.hip", "pbp_r10_decoder.h", "pbp_r10.h")),
+              _csrc("pbp_r10.hip", "pbp_r10_decoder.h", "pbp_r10.h",
+                    "pbp_arith.h")),
     "n16384": ("traffic_bp_decode_n16384_2db.txt",
                _csrc("pbp_decode.hip", "pbp_generic_decoder.h")),
     "unrolled": ("traffic_unrolled_backward_n1024.txt",
@@ -60,7 +61,7 @@ TRAFFIC_RECORDS = {
     # (one per rate) per decode, summed
     "mixed": ("traffic_class_pair_n4096_mixed.txt",
               _csrc("pbp_mixed.hip", "pbp_pair_decoder.h",
-                    "pbp_generic_decoder.h")),
+                    "pbp_generic_decoder.h", "pbp_arith.h")),
 }
 KERNEL_SRCS = TRAFFIC_RECORDS["n1024"][1]
 
@@ -71,12 +72,14 @@ KERNEL_SRCS = TRAFFIC_RECORDS["n1024"][1]
 TRACE_RECORDS = {
     "n1024": ("bp_decode_r10_n1024_3db_trace.md", KERNEL_SRCS),
     "c1": ("bp_decode_n64_c1_trace.md",
-           _csrc("pbp_decode.hip", "pbp_generic_decoder.h")),
+           _csrc("pbp_decode.hip", "pbp_wave_decoder.h", "pbp_arith.h",
+                 "pbp_generic_decoder.h")),
     "n16384": ("n16384_trace.md",
                _csrc("pbp_decode.hip", "pbp_generic_decoder.h")),
     "sc": ("sc_decode_n1024_trace.md", _csrc("pbp_sc.hip")),
     "quant": ("quant_decode_n1024_3db_trace.md",
-              _csrc("pbp_quant.hip", "pbp_r10_decoder.h", "pbp_r10.h")),
+              _csrc("pbp_quant.hip", "pbp_r10_decoder.h", "pbp_r10.h",
+                    "pbp_arith.h")),
     "round_trip": ("round_trip_trace.md", _csrc("pbp_roundtrip.hip")),
     "mixed": ("mixed_trace.md", TRAFFIC_RECORDS["mixed"][1]),
     "unrolled": ("unrolled_trace.md", TRAFFIC_RECORDS["unrolled"][1]),

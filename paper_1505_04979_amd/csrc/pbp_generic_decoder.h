@@ -146,6 +146,10 @@ struct DecodeParams {
     float *soft_out;
     float *state;          // global L state (when not in LDS)
     int64_t state_stride;  // floats per workgroup slot
+    // fixed-point messages only (decoders with the Fixed arithmetic policy)
+    float qmax;            // Q = 2^(b-1) - 1
+    int32_t frac;          // fraction bits of the channel quantizer
+    int8_t *soft_q;        // B x N or null: sat(R + L) at column m+1
 };
 
 // Control words kept in LDS (16-byte aligned size, so the float columns after

@@ -21,7 +21,7 @@
 //    (-1)^u inf on rows frozen at stage m (from the kept decisions).
 // With m odd the last stage runs alone on rows 4t .. 4t+3.
 //
-// The schedule, the PE arithmetic (pe_eq1), the CSFG walk and the stop test
+// The schedule, the PE arithmetic (eq. (1) through the arithmetic policy), the CSFG walk and the stop test
 // are those of the generic decoder, so results agree bit for bit.  LDS: the
 // odd columns ((m-1)/2 columns of N floats), two R columns and two columns
 // of check inputs used in turn, four bit words per 64 rows (one of them the
@@ -39,6 +39,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "pbp_arith.h"
 #include "pbp_generic_decoder.h"
 #include "pbp_internal.h"
 
@@ -51,9 +52,7 @@ using generic::DecodeParams;
 using generic::ffx_cross;
 using generic::ffx_word;
 using generic::kBatch;
-using generic::kInf;
 using generic::kMaxWordsPerLane;
-using generic::pe_eq1;
 using generic::shfl_xor64;
 
 template <int M>
@@ -78,7 +77,9 @@ __host__ __device__ constexpr size_t lds_bytes()
            sizeof(float) * (size_t)(4 + Shape<M>::NL) * Shape<M>::N;
 }
 
-template <int M>
+// Ar: the message arithmetic (pbp_arith.h); arith::Fixed decodes b-bit
+// integers, +-Q standing for the +-inf of frozen rows
+template <int M, class Ar = arith::F32>
 struct Decoder {
     using S = Shape<M>;
     static constexpr int N = S::N, NT = S::NT, NW = S::NW, NP = S::NP;
@@ -125,6 +126,9 @@ struct Decoder {
 
     __device__ __forceinline__ float *rcol(int b) const { return Rb + b * N; }
 
+    // the message standing for inf: +inf, or Q in fixed point
+    __device__ __forceinline__ float big() const { return Ar::big(P.qmax); }
+
     // L at odd column c, 3 <= c <= m
     __device__ __forceinline__ float *lcol(int c) const
     {
@@ -150,8 +154,8 @@ struct Decoder {
     __device__ __forceinline__ float prior(int i) const
     {
         if (i < p[M])
-            return ((dw[i >> 6] >> (i & 63)) & 1) ? -kInf : kInf;
-        return ((fw[i >> 6] >> (i & 63)) & 1) ? kInf : 0.0f;
+            return ((dw[i >> 6] >> (i & 63)) & 1) ? -big() : big();
+        return ((fw[i >> 6] >> (i & 63)) & 1) ? big() : 0.0f;
     }
 
     // ---- CSFG walk at stage J (Section III, eqs. (2)-(4)) ----
@@ -430,7 +434,7 @@ struct Decoder {
             ran[e] = J == 1 || rows[ka] >= fJ;
             if (ran[e]) {
                 float oLa, oLb, oRa, oRb;
-                pe_eq1(Lr[PI][ka], Lr[PI][kb], Rv[ka], Rv[kb], alpha, oLa, oLb,
+                Ar::pe(Lr[PI][ka], Lr[PI][kb], Rv[ka], Rv[kb], alpha, P.qmax, oLa, oLb,
                        oRa, oRb);
                 lj[ka] = J == 1 ? Rv[ka] + oLa : oLa;
                 lj[kb] = J == 1 ? Rv[kb] + oLb : oLb;
@@ -476,7 +480,7 @@ struct Decoder {
                 const int ka = 2 * e, kb = 2 * e + 1;
                 if (rows[ka] >= fJ1) {
                     float oLa, oLb, oRa, oRb;
-                    pe_eq1(Lin[ka], Lin[kb], Rv[ka], Rv[kb], alpha, oLa, oLb,
+                    Ar::pe(Lin[ka], Lin[kb], Rv[ka], Rv[kb], alpha, P.qmax, oLa, oLb,
                            oRa, oRb);
                     Lr[PI][ka] = oLa;
                     Lr[PI][kb] = oLb;
@@ -559,7 +563,7 @@ struct Decoder {
 #pragma unroll
             for (int k = 0; k < 4; k++)
                 if (rows[k] >= lo && rows[k] < hi)
-                    Lr[PI][k] = vv[k] < 0.0f ? -kInf : kInf;
+                    Lr[PI][k] = vv[k] < 0.0f ? -big() : big();
         }
         pe += (N - (p[J] << (M - J))) >> 1;
 
@@ -580,7 +584,7 @@ struct Decoder {
                         float *Lc = lcol(J + 2);
                         const int r0 = pj1s << SB;
                         for (int i = tid; i < (1 << SB); i += NT)
-                            Lc[r0 + i] = ((xpJ1[i >> 6] >> (i & 63)) & 1) ? -kInf : kInf;
+                            Lc[r0 + i] = ((xpJ1[i >> 6] >> (i & 63)) & 1) ? -big() : big();
                     }
                     p[J + 1] = pj1s + 1;
                     if (P.freeze_walk == 0)
@@ -593,7 +597,7 @@ struct Decoder {
                                 return P.freeze_input ? Rout[i] + Lc[i] : Rout[i];
                             };
                             walk<J + 1>(pj1s + 1, vin,
-                                        [&](int i, bool x) { Lc[i] = x ? -kInf : kInf; });
+                                        [&](int i, bool x) { Lc[i] = x ? -big() : big(); });
                         } else {
                             auto vin = [&](int i) {
                                 return P.freeze_input ? Rout[i] + prior(i) : Rout[i];
@@ -614,7 +618,7 @@ struct Decoder {
                         return P.freeze_input ? Rout[i] + Lc[i] : Rout[i];
                     };
                     walk<J + 1>(pj1, vin,
-                                [&](int i, bool x) { Lc[i] = x ? -kInf : kInf; });
+                                [&](int i, bool x) { Lc[i] = x ? -big() : big(); });
                 } else {
                     auto vin = [&](int i) {
                         return P.freeze_input ? Rout[i] + prior(i) : Rout[i];
@@ -661,7 +665,7 @@ struct Decoder {
             ran[e] = rows[ka] >= fJ;
             if (ran[e]) {
                 float oLa, oLb, oRa, oRb;
-                pe_eq1(Lin[ka], Lin[kb], Rv[ka], Rv[kb], alpha, oLa, oLb, oRa,
+                Ar::pe(Lin[ka], Lin[kb], Rv[ka], Rv[kb], alpha, P.qmax, oLa, oLb, oRa,
                        oRb);
                 lj[ka] = oLa;
                 lj[kb] = oLb;
@@ -749,7 +753,7 @@ struct Decoder {
             rows_of<M - 2>(rows);
 #pragma unroll
             for (int k = 0; k < 4; k++)
-                chv[k] = ch[rows[k]];
+                chv[k] = Ar::channel(ch[rows[k]], P.frac, P.qmax);
         }
         for (int w = tid; w < NW; w += NT)
             fw[w] = P.frozen_words[w];
@@ -797,10 +801,18 @@ struct Decoder {
             out[k] = i < fm ? (uint8_t)((dw[i >> 6] >> (i & 63)) & 1)
                             : (uint8_t)(Rf[i] < 0.0f);
         }
-        if (P.soft_out) {
+        if constexpr (Ar::kFixed) {
+            if (P.soft_q) {
+                // sat(R + L) at column m+1 (+-Q inside frozen CSFGs), as bytes
+                int8_t *so = P.soft_q + frame * N;
+                for (int i = tid; i < N; i += NT)
+                    so[i] = (int8_t)(int)(i < fm ? (((dw[i >> 6] >> (i & 63)) & 1) ? -big() : big())
+                                                 : Ar::sat(Rf[i] + prior(i), P.qmax));
+            }
+        } else if (P.soft_out) {
             float *so = P.soft_out + frame * N;
             for (int i = tid; i < N; i += NT)
-                so[i] = i < fm ? (((dw[i >> 6] >> (i & 63)) & 1) ? -kInf : kInf)
+                so[i] = i < fm ? (((dw[i >> 6] >> (i & 63)) & 1) ? -big() : big())
                                : Rf[i] + prior(i);
         }
         if (tid == 0) {

@@ -7,12 +7,13 @@
 // sum of eq. (1) saturates; +-Q stands for the +-inf of the frozen prior and
 // of a frozen CSFG's messages; hard decisions take the exact sum's sign.
 //
-// N = 1024 runs the register-resident decoder of pbp_decode with the
-// fixed-point message arithmetic (pbp_r10_decoder.h, ArithFixed): messages
-// are integers held exactly in FP32 registers, so the PE is the FP32 one plus
-// a saturation per sum and a rounding per scaled minimum.
+// N <= 64, 1024, 2048 and 4096 run the on-chip decoders of pbp_decode
+// (pbp_wave_decoder.h, pbp_r10_decoder.h, pbp_pair_decoder.h) with the
+// fixed-point arithmetic policy (pbp_arith.h): messages are integers held
+// exactly in FP32 registers, so the PE is the FP32 one plus a saturation per
+// sum and a rounding per scaled minimum.
 //
-// Other lengths: one wavefront per frame, persistent over a grid stride,
+// N = 128..512: one wavefront per frame, persistent over a grid stride,
 // with the whole state in LDS, one signed byte per message (L at columns
 // 1..m+1, the working R column updated in place stage by stage, the
 // quantized channel, the kept decisions and two bit-byte scratch columns):
@@ -24,8 +25,10 @@
 #include <hip/hip_runtime.h>
 
 #include "pbp_internal.h"
+#include "pbp_pair_decoder.h"
 #include "pbp_r10.h"
 #include "pbp_r10_decoder.h"
+#include "pbp_wave_decoder.h"
 
 namespace {
 
@@ -346,6 +349,111 @@ hipError_t launch_quant_r10(const pbp_code *c, const QParams &Q, float alpha_q,
     return hipGetLastError();
 }
 
+// the generic parameter block of the wavefront and workgroup decoders
+pbp::generic::DecodeParams decode_params(const pbp_code *c, const QParams &Q,
+                                         float alpha_q)
+{
+    pbp::generic::DecodeParams P{};
+    P.llr = Q.llr;
+    P.B = Q.B;
+    P.frozen_words = c->d_frozen_words;
+    P.info_pos = Q.info_pos;
+    P.K = Q.K;
+    P.max_iter = Q.max_iter;
+    P.early_stop = Q.early_stop;
+    P.freezing = Q.freezing;
+    P.freeze_input = Q.freeze_input;
+    P.freeze_walk = Q.freeze_walk;
+    P.alpha = alpha_q;
+    P.info_out = Q.info_out;
+    P.iters_out = Q.iters_out;
+    P.pe_out = Q.pe_out;
+    P.soft_out = nullptr;
+    P.qmax = (float)Q.Q;
+    P.frac = Q.frac;
+    P.soft_q = Q.soft_out;
+    return P;
+}
+
+// N <= 64: one wavefront per frame, every message in registers
+template <int M>
+hipError_t launch_quant_wave(const pbp_code *c, const QParams &Q, float alpha_q,
+                             hipStream_t st)
+{
+    const pbp::generic::DecodeParams P = decode_params(c, Q, alpha_q);
+    int64_t grid = P.B;
+    if (grid > (1ll << 30))
+        grid = 1ll << 30;
+    if (P.freezing)
+        hipLaunchKernelGGL((pbp::wave::bp_decode_wave_kernel<M, true, pbp::arith::Fixed>),
+                           dim3((unsigned)grid), dim3(64), 0, st, P);
+    else
+        hipLaunchKernelGGL((pbp::wave::bp_decode_wave_kernel<M, false, pbp::arith::Fixed>),
+                           dim3((unsigned)grid), dim3(64), 0, st, P);
+    return hipGetLastError();
+}
+
+// N = 2048, 4096: one workgroup of N/4 threads per frame, messages on chip;
+// frames from the stream's counter pair, which the last group out rewinds
+template <int M>
+__global__ __launch_bounds__(pbp::pair::Shape<M>::NT) void quant_pair_kernel(
+    pbp::generic::DecodeParams P, int *counter)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ int s_frame;
+    const int tid = (int)threadIdx.x;
+    pbp::pair::Decoder<M, pbp::arith::Fixed> D(P, smem, tid);
+    int64_t frame = blockIdx.x;
+    for (;;) {
+        if (counter) {
+            if (tid == 0)
+                s_frame = atomicAdd(counter, 1);
+            __syncthreads();
+            frame = s_frame;
+            __syncthreads();
+        }
+        if (frame >= P.B)
+            break;
+        D.decode(frame);
+        if (!counter)
+            frame += gridDim.x;
+    }
+    if (counter && tid == 0 &&
+        atomicAdd(counter + 1, 1) == (int)gridDim.x - 1) {
+        atomicExch(counter, 0);
+        atomicExch(counter + 1, 0);
+    }
+}
+
+template <int M>
+hipError_t launch_quant_pair(const pbp_code *c, const QParams &Q, float alpha_q,
+                             int *counter, hipStream_t st)
+{
+    using S = pbp::pair::Shape<M>;
+    const pbp::generic::DecodeParams P = decode_params(c, Q, alpha_q);
+    const size_t lds = pbp::pair::lds_bytes<M>();
+    auto kern = quant_pair_kernel<M>;
+    hipError_t e = hipFuncSetAttribute((const void *)kern,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)lds);
+    if (e != hipSuccess)
+        return e;
+    static int occ = 0;
+    if (occ < 1) {
+        int o = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&o, (const void *)kern,
+                                                         S::NT, lds) != hipSuccess)
+            return hipGetLastError();
+        occ = o < 1 ? 1 : o;
+    }
+    int64_t grid = (int64_t)c->cus * occ;
+    if (grid > P.B)
+        grid = P.B;
+    int *ctr = P.B <= (int64_t(1) << 30) ? counter : nullptr;
+    hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(S::NT), lds, st, P, ctr);
+    return hipGetLastError();
+}
+
 }  // namespace
 
 extern "C" int32_t pbp_decode_quant(const pbp_code *code, const float *llr,
@@ -389,32 +497,40 @@ extern "C" int32_t pbp_decode_quant(const pbp_code *code, const float *llr,
     P.pe_out = pe_out;
     P.soft_out = soft_out;
     hipStream_t st = (hipStream_t)stream;
-    if (code->m == pbp::r10::M) {
+    const float alpha_q = (float)P.a16 / 16.0f;     // exact
+    // on-chip decoders with every message an integer in an FP32 register
+    if (code->m <= 6) {
+        hipError_t e;
+        switch (code->m) {
+        case 1: e = launch_quant_wave<1>(code, P, alpha_q, st); break;
+        case 2: e = launch_quant_wave<2>(code, P, alpha_q, st); break;
+        case 3: e = launch_quant_wave<3>(code, P, alpha_q, st); break;
+        case 4: e = launch_quant_wave<4>(code, P, alpha_q, st); break;
+        case 5: e = launch_quant_wave<5>(code, P, alpha_q, st); break;
+        default: e = launch_quant_wave<6>(code, P, alpha_q, st); break;
+        }
+        return e == hipSuccess ? PBP_OK : PBP_EDEVICE;
+    }
+    if (code->m == pbp::r10::M || code->m == 11 || code->m == 12) {
         pbp::Workspace ws;
         const int32_t rc = pbp::stream_workspace(code, st, &ws);
         if (rc != PBP_OK)
             return rc;
-        const hipError_t e = launch_quant_r10(code, P, (float)P.a16 / 16.0f,
-                                              ws.counter, st);
+        const hipError_t e =
+            code->m == pbp::r10::M ? launch_quant_r10(code, P, alpha_q, ws.counter, st)
+            : code->m == 11      ? launch_quant_pair<11>(code, P, alpha_q, ws.counter, st)
+                                 : launch_quant_pair<12>(code, P, alpha_q, ws.counter, st);
         return e == hipSuccess ? PBP_OK : PBP_EDEVICE;
     }
-    // the LDS path keeps messages as bytes: a scaled minimum must fit
-    // (8-bit messages with alpha above 1 can reach 246)
+    // N = 128..512 keep messages as bytes: a scaled minimum must fit (8-bit
+    // messages with alpha above 1 can reach 246)
     if ((P.a16 * P.Q + 8) >> 4 > 127)
         return PBP_EUNSUPPORTED;
     hipError_t e;
     switch (code->m) {
-    case 1: e = launch_quant<1>(code, P, st); break;
-    case 2: e = launch_quant<2>(code, P, st); break;
-    case 3: e = launch_quant<3>(code, P, st); break;
-    case 4: e = launch_quant<4>(code, P, st); break;
-    case 5: e = launch_quant<5>(code, P, st); break;
-    case 6: e = launch_quant<6>(code, P, st); break;
     case 7: e = launch_quant<7>(code, P, st); break;
     case 8: e = launch_quant<8>(code, P, st); break;
     case 9: e = launch_quant<9>(code, P, st); break;
-    case 11: e = launch_quant<11>(code, P, st); break;
-    case 12: e = launch_quant<12>(code, P, st); break;
     default: return PBP_EUNSUPPORTED;
     }
     return e == hipSuccess ? PBP_OK : PBP_EDEVICE;

@@ -34,6 +34,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include "pbp_arith.h"
 #include "pbp_internal.h"
 #include "pbp_r10.h"
 
@@ -43,21 +44,10 @@ namespace {
 
 constexpr float kInf = __builtin_inff();
 
-// sign(y) min(|x|, |y|): y clamped to [-|x|, |x|] (a selection, exact)
-__device__ __forceinline__ float clampm(float x, float y)
-{
-    return __builtin_amdgcn_fmed3f(-fabsf(x), y, fabsf(x));
-}
-
-// alpha carrying the sign of x.  The min-sum term of eq. (1),
-// alpha sign(x) sign(y) min(|x|, |y|), is salpha(x) * clampm(x, y): one
-// product, rounded once and symmetrically in sign.  A PE's two terms with
-// the same first operand share salpha, so a PE costs 11 FP32 operations.  A
-// zero result may carry either sign; no value or decision depends on it.
-__device__ __forceinline__ float salpha(float x, float alpha)
-{
-    return __builtin_copysignf(alpha, x);
-}
+using arith::clampm;
+using arith::salpha;
+using ArithF32 = arith::F32;
+using ArithFixed = arith::Fixed;
 
 __device__ __forceinline__ void wave_sync()
 {
@@ -106,69 +96,6 @@ struct Params {
     float qmax;            // Q = 2^(b-1) - 1
     int32_t frac;          // fraction bits of the channel quantizer
     int8_t *soft_q;        // B x N or null: sat(R + L) at column M+1
-};
-
-// Message arithmetic.  ArithF32 is eq. (1) in FP32 min-sum.  ArithFixed runs
-// the same decoder on saturating b-bit integers (Sections I and V: the
-// hardware setting in which the paper counts a PE): every message is an
-// integer in [-Q, Q], held exactly in an FP32 register (all sums, products
-// and thresholds stay far below 2^24), the +-inf of frozen rows become +-Q,
-// and hard decisions keep the exact sum's sign.
-struct ArithF32 {
-    static constexpr bool kFixed = false;
-    __device__ static __forceinline__ float big(const Params &) { return kInf; }
-    __device__ static __forceinline__ float channel(float v, const Params &) { return v; }
-    __device__ static __forceinline__ void pe(float La, float Lb, float Ra, float Rb,
-                                              const Params &P, float &la, float &lbv,
-                                              float &ra, float &rb)
-    {
-        const float alpha = P.alpha;
-        const float s = Lb + Rb;
-        const float aLa = salpha(La, alpha);
-        const float g1 = aLa * clampm(La, Ra);
-        la = aLa * clampm(La, s);
-        lbv = Lb + g1;
-        ra = salpha(Ra, alpha) * clampm(Ra, s);
-        rb = Rb + g1;
-    }
-};
-
-struct ArithFixed {
-    static constexpr bool kFixed = true;
-    __device__ static __forceinline__ float big(const Params &P) { return P.qmax; }
-    __device__ static __forceinline__ float sat(float v, float q)
-    {
-        return __builtin_amdgcn_fmed3f(v, -q, q);
-    }
-    // channel: clamp(round(LLR 2^F), -Q, Q), halves away from zero (the
-    // product by 2^F is exact)
-    __device__ static __forceinline__ float channel(float v, const Params &P)
-    {
-        return sat(roundf(ldexpf(v, P.frac)), P.qmax);
-    }
-    // sign(x) sign(y) floor((a min(|x|, |y|) + 8) / 16), a = round(16 alpha):
-    // t = (a/16) sign(x) clampm(x, y) is a multiple of 1/16 computed exactly,
-    // and trunc(t + copysign(1/2, t)) = sign(t) floor(|t| + 1/2)
-    __device__ static __forceinline__ float term(float sa, float x, float y)
-    {
-        const float t = sa * clampm(x, y);
-        return truncf(t + __builtin_copysignf(0.5f, t));
-    }
-    // one PE of eq. (1): every sum saturates, the scaled minima do not
-    __device__ static __forceinline__ void pe(float La, float Lb, float Ra, float Rb,
-                                              const Params &P, float &la, float &lbv,
-                                              float &ra, float &rb)
-    {
-        const float a = P.alpha;           // round(16 alpha) / 16, exact
-        const float q = P.qmax;
-        const float s = sat(Lb + Rb, q);
-        const float aLa = salpha(La, a);
-        const float g1 = term(aLa, La, Ra);
-        la = term(aLa, La, s);
-        lbv = sat(Lb + g1, q);
-        ra = term(salpha(Ra, a), Ra, s);
-        rb = sat(Rb + g1, q);
-    }
 };
 
 // LDS per wavefront
@@ -314,7 +241,7 @@ struct Decoder {
     // still be read, so only those consult the kept decisions.
     __device__ __forceinline__ float l11(int q, int lo, int hi) const
     {
-        const float big = Ar::big(P);
+        const float big = Ar::big(P.qmax);
         float v = fzbit(MA, q) ? big : 0.0f;
         if (FRZ) {
             const int rq = rowq(MA, q);
@@ -351,15 +278,15 @@ struct Decoder {
 #pragma unroll
             for (int qh = 0; qh < 4; qh++) {
                 const float4 v = *reinterpret_cast<const float4 *>(src + qh * 256 + lane * 4);
-                ch[qh * 4 + 0] = Ar::channel(v.x, P);
-                ch[qh * 4 + 1] = Ar::channel(v.y, P);
-                ch[qh * 4 + 2] = Ar::channel(v.z, P);
-                ch[qh * 4 + 3] = Ar::channel(v.w, P);
+                ch[qh * 4 + 0] = Ar::channel(v.x, P.frac, P.qmax);
+                ch[qh * 4 + 1] = Ar::channel(v.y, P.frac, P.qmax);
+                ch[qh * 4 + 2] = Ar::channel(v.z, P.frac, P.qmax);
+                ch[qh * 4 + 3] = Ar::channel(v.w, P.frac, P.qmax);
             }
         } else {
 #pragma unroll
             for (int q = 0; q < Q; q++)
-                ch[q] = Ar::channel(src[(q >> 2) * 256 + lane * 4 + (q & 3)], P);
+                ch[q] = Ar::channel(src[(q >> 2) * 256 + lane * 4 + (q & 3)], P.frac, P.qmax);
         }
     }
 
@@ -423,7 +350,7 @@ struct Decoder {
         const float Ra = (J == 1) ? ch[QA] : R[QA];
         const float Rb = (J == 1) ? ch[QB] : R[QB];
         float la, lbv, ra, rb;
-        Ar::pe(La, Lb, Ra, Rb, P, la, lbv, ra, rb);
+        Ar::pe(La, Lb, Ra, Rb, P.alpha, P.qmax, la, lbv, ra, rb);
         R[QA] = ra;
         R[QB] = rb;
         if constexpr (J == 1) {
@@ -676,7 +603,7 @@ struct Decoder {
                     S.dec[lr[MP] + rq] = (uint8_t)(lane_fx(W[i]) & 1u);
                     if constexpr (lbcol(J + 1) >= 0)
                         S.lb[lbcol(J + 1)][sl[MP] ^ swz(rq)] =
-                            ((X0[i] >> lane) & 1) ? -Ar::big(P) : Ar::big(P);
+                            ((X0[i] >> lane) & 1) ? -Ar::big(P.qmax) : Ar::big(P.qmax);
                 }
             }
         }
@@ -697,7 +624,7 @@ struct Decoder {
             for (int q = 0; q < Q; q++) {
                 const int rq = rowq(MP, q);
                 if (rq + lanemax(MP) >= lo && rq < hi) {
-                    const float fixed = check_input<J>(q) < 0.0f ? -Ar::big(P) : Ar::big(P);
+                    const float fixed = check_input<J>(q) < 0.0f ? -Ar::big(P.qmax) : Ar::big(P.qmax);
                     Ln[q] = (lr[MP] >= opaque_s(lo - rq) && lr[MP] < opaque_s(hi - rq))
                                 ? fixed : Ln[q];
                 }

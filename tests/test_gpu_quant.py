@@ -1,7 +1,8 @@
 """GPU parity of the fixed-point decoder (pbp_decode_quant) with the
 oracle's, through the C-ABI: decided bits, iteration counts, PE counts and
 the saturated posteriors all equal (integer arithmetic, so exact), in every
-mode and three message formats, for N = 2 to 4096 including degenerate
+mode and three message formats, for N = 2 to 4096 (every on-chip decoder
+and the byte-LDS kernel) including degenerate
 rates and noiseless frames; the long-code limit is rejected."""
 
 import numpy as np
@@ -53,8 +54,10 @@ def run(env, N, K, llr, bits, frac, mode):
 
 @pytest.mark.parametrize("mode", list(MODES))
 @pytest.mark.parametrize("N,K,ebn0,B", [(2, 1, 2.0, 100), (8, 4, 2.0, 100),
+                                        (32, 16, 2.0, 200),
                                         (64, 32, 2.5, 200), (256, 128, 2.5, 100),
                                         (1024, 512, 3.0, 60),
+                                        (2048, 1024, 2.5, 12),
                                         (4096, 2048, 2.5, 8)])
 def test_quant_parity(env, N, K, ebn0, B, mode):
     print(f"[quant] N={N} K={K} mode={mode}", flush=True)
@@ -98,15 +101,15 @@ def test_quant_rejects(env):
                              bits=9)
 
 
-def test_quant_alpha_above_one(env):
+@pytest.mark.parametrize("N,K,B", [(64, 32, 200), (1024, 512, 40),
+                                   (4096, 2048, 6)])
+def test_quant_alpha_above_one(env, N, K, B):
     """alpha = 1.25 (a = 20) with 8-bit messages: a scaled minimum reaches
     (20 * 127 + 8) >> 4 = 159 > Q.  The oracle keeps it unsaturated, and the
-    N = 1024 register decoder holds it exactly; the byte-LDS kernel of the
-    other lengths cannot, and rejects the format."""
+    on-chip decoders hold it exactly in FP32 registers."""
     pbp, torch = env
-    N, K = 1024, 512
     fz = frozen_mask(N, K)
-    _, _, llr = make_frames(N, K, 40, 2.5, stream=1400)
+    _, _, llr = make_frames(N, K, B, 2.5, stream=1400 + N)
     code = pbp.Code(N, K, fz)
     for mode in ("plain", "es_frz"):
         o = dict(freeze_input=1, freeze_walk=0, alpha=1.25)
@@ -119,12 +122,17 @@ def test_quant_alpha_above_one(env):
         assert np.array_equal(got["pe"].cpu().numpy(), ref["pe"])
         assert np.array_equal(got["soft"].cpu().numpy().astype(np.int32),
                               ref["soft"])
-    short = pbp.Code(64, 32, frozen_mask(64, 32))
+
+
+def test_quant_byte_format_limit(env):
+    """N = 128..512 keep each message as a byte in LDS: 8-bit messages with
+    alpha = 1.25 are rejected there; 7-bit ones fit at any alpha below 2."""
+    pbp, torch = env
+    code = pbp.Code(256, 128, frozen_mask(256, 128))
     with pytest.raises(pbp.PbpError):
-        pbp.pbp_decode_quant(short, torch.zeros((1, 64), device="cuda"),
+        pbp.pbp_decode_quant(code, torch.zeros((1, 256), device="cuda"),
                              bits=8, alpha=1.25)
-    # 7-bit messages fit a byte at any alpha below 2
-    pbp.pbp_decode_quant(short, torch.zeros((1, 64), device="cuda"), bits=7,
+    pbp.pbp_decode_quant(code, torch.zeros((1, 256), device="cuda"), bits=7,
                          alpha=1.25)
 
 
