@@ -705,7 +705,7 @@ def bench_c1(args, pbp, torch):
         pe_per_frame=round(float(pe.mean()), 1), fer=errs / B,
         ms_per_step_median=round(med, 4), end_to_end_ms=round(e2e, 3),
         parity=parity,
-        roofline=_alu_roofline(achieved, "c1", "bp_decode_wave_kernel<6, false>",
+        roofline=_alu_roofline(achieved, "c1", "bp_decode_wave_kernel<6, false, F32>",
                                B, ms, "12 operations per PE activation"))
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(llr, K, out["info"], opts,
