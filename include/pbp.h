@@ -196,18 +196,15 @@ int32_t pbp_decode_round_trip(const pbp_code *code, const float *llr,
  * hard decisions take the exact sum's sign.  Same schedule, stop test,
  * freezing walk, iteration and PE counts as pbp_decode.  The scaled minimum
  * itself is not saturated (above 1, alpha can lift it past Q).
- *   bits      2..8; frac 0..16
+ *   bits      2..8 (the posteriors are returned as bytes); frac 0..16
  *   soft_out  device, B x N int8, or NULL: sat(R + L) at column m+1 (+-Q
  *             inside frozen CSFGs)
- * N <= 64, 1024, 2048 and 4096 run pbp_decode's on-chip decoders with the
- * integers held exactly in FP32 registers (N >= 1024 take frames from the
- * stream's workspace counter: calls on one stream are ordered, as for
- * pbp_decode).  N = 128..512 keep every message as a byte in LDS, so they
- * reject formats whose scaled minimum can exceed 127 (bits = 8 with alpha
- * above 1.03).
+ * Every length runs the on-chip decoder pbp_decode uses for it, with the
+ * integers held exactly in FP32 registers and LDS words (N >= 1024 take
+ * frames from the stream's workspace counter: calls on one stream are
+ * ordered, as for pbp_decode).
  * Other arguments as pbp_decode.  N <= 4096.
- * Errors: as pbp_decode; PBP_EUNSUPPORTED for N > 4096, and for
- * N = 128..512 with (round(16 alpha) Q + 8) >> 4 > 127. */
+ * Errors: as pbp_decode; PBP_EUNSUPPORTED for N > 4096. */
 int32_t pbp_decode_quant(const pbp_code *code, const float *llr, int64_t B,
                          const pbp_decode_opts *opts, int32_t bits,
                          int32_t frac, uint8_t *info_out, int32_t *iters_out,

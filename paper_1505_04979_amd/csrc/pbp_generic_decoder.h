@@ -19,6 +19,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "pbp_arith.h"
 #include "pbp_internal.h"
 
 namespace pbp {
@@ -220,7 +221,9 @@ __host__ __device__ constexpr int64_t slot_floats(int state)
 // frame).  smem: this instance's LDS (lds_bytes); gslot: its device slot
 // (slot_floats, STATE > 0).  tid, NT: thread index and count of the group
 // decoding the frame (NT = 64 when WAVE).
-template <int M, int STATE, bool WAVE>
+// Ar: the message arithmetic (pbp_arith.h); arith::Fixed decodes b-bit
+// integers (state in LDS only), +-Q standing for the +-inf of frozen rows
+template <int M, int STATE, bool WAVE, class Ar = arith::F32>
 __device__ __forceinline__ void decode_frame(const DecodeParams &P,
                                              int64_t frame,
                                              unsigned char *smem,
@@ -242,6 +245,8 @@ __device__ __forceinline__ void decode_frame(const DecodeParams &P,
     const int wv = tid >> 6;       // wavefront of the group
     const int nwv = NT >> 6;       // wavefronts in the group
     const float alpha = P.alpha;
+    const float big = Ar::big(P.qmax);     // inf, or Q in fixed point
+    static_assert(!Ar::kFixed || STATE == 0, "fixed point keeps its state in LDS");
     // an opaque thread count keeps the strided loops rolled (a known count
     // of 64 would unroll them N/64 times over and exhaust the registers)
     NT = __builtin_amdgcn_readfirstlane(NT);
@@ -253,10 +258,10 @@ __device__ __forceinline__ void decode_frame(const DecodeParams &P,
     // ---- initial messages ----
     for (int i = tid; i < N; i += NT) {
         if (STATE == 0)
-            chl[i] = llr[i];
+            chl[i] = Ar::channel(llr[i], P.frac, P.qmax);
         for (int c = 1; c <= M; c++)
             Lc(c)[i] = 0.0f;
-        Lc(M + 1)[i] = frozen_bit(P.frozen_words, i) ? kInf : 0.0f;
+        Lc(M + 1)[i] = frozen_bit(P.frozen_words, i) ? big : 0.0f;
     }
     for (int w = tid; w < NW; w += NT)
         dw[w] = 0;
@@ -313,13 +318,13 @@ __device__ __forceinline__ void decode_frame(const DecodeParams &P,
                     for (int u = 0; u < kBatch; u++) {
                         if (q0 + u * NT < N / 2) {
                             const int a = ia[u], b = a + h;
-                            const float sm = Lb[u] + Rb[u];
-                            const float aLa = salpha(La[u], alpha);
-                            const float g1 = gmin(aLa, La[u], Ra[u]);
-                            Lj[a] = gmin(aLa, La[u], sm);
-                            Lj[b] = Lb[u] + g1;
-                            Rw[a] = gmin(salpha(Ra[u], alpha), Ra[u], sm);
-                            Rw[b] = Rb[u] + g1;
+                            float oLa, oLb, oRa, oRb;
+                            Ar::pe(La[u], Lb[u], Ra[u], Rb[u], alpha, P.qmax,
+                                   oLa, oLb, oRa, oRb);
+                            Lj[a] = oLa;
+                            Lj[b] = oLb;
+                            Rw[a] = oRa;
+                            Rw[b] = oRb;
                         }
                     }
                 }
@@ -349,13 +354,13 @@ __device__ __forceinline__ void decode_frame(const DecodeParams &P,
                         if (g0 + u * NT < N / 8) {
                             const int a = ia[u], b = a + h;
                             float4 oLa, oLb, oRa, oRb;
-                            pe_eq1(La[u].x, Lb[u].x, Ra[u].x, Rb[u].x, alpha,
+                            Ar::pe(La[u].x, Lb[u].x, Ra[u].x, Rb[u].x, alpha, P.qmax,
                                    oLa.x, oLb.x, oRa.x, oRb.x);
-                            pe_eq1(La[u].y, Lb[u].y, Ra[u].y, Rb[u].y, alpha,
+                            Ar::pe(La[u].y, Lb[u].y, Ra[u].y, Rb[u].y, alpha, P.qmax,
                                    oLa.y, oLb.y, oRa.y, oRb.y);
-                            pe_eq1(La[u].z, Lb[u].z, Ra[u].z, Rb[u].z, alpha,
+                            Ar::pe(La[u].z, Lb[u].z, Ra[u].z, Rb[u].z, alpha, P.qmax,
                                    oLa.z, oLb.z, oRa.z, oRb.z);
-                            pe_eq1(La[u].w, Lb[u].w, Ra[u].w, Rb[u].w, alpha,
+                            Ar::pe(La[u].w, Lb[u].w, Ra[u].w, Rb[u].w, alpha, P.qmax,
                                    oLa.w, oLb.w, oRa.w, oRb.w);
                             st4(Lj + a, oLa);
                             st4(Lj + b, oLb);
@@ -414,7 +419,7 @@ __device__ __forceinline__ void decode_frame(const DecodeParams &P,
                         if (h <= 64) {
                             // passed: keep uhat, L at column j+1 := (-1)^xhat inf
                             if (tid < h)
-                                L1[r0 + tid] = ((xl >> tid) & 1) ? -kInf : kInf;
+                                L1[r0 + tid] = ((xl >> tid) & 1) ? -big : big;
                             if (tid == 0) {
                                 const uint64_t msk = (h == 64 ? ~0ull : ((1ull << h) - 1))
                                                      << (r0 & 63);
@@ -505,7 +510,7 @@ __device__ __forceinline__ void decode_frame(const DecodeParams &P,
                     // freeze: L at column j+1 := (-1)^xhat inf
                     for (int i = tid; i < h; i += NT) {
                         const bool x = (xw[i >> 6] >> (i & 63)) & 1;
-                        L1[r0 + i] = x ? -kInf : kInf;
+                        L1[r0 + i] = x ? -big : big;
                     }
                     pj++;
                     if (P.freeze_walk == 0) {
@@ -621,11 +626,20 @@ __device__ __forceinline__ void decode_frame(const DecodeParams &P,
         out[k] = i < fm ? (uint8_t)((dw[i >> 6] >> (i & 63)) & 1)
                         : (uint8_t)(Rw[i] < 0.0f);
     }
-    if (P.soft_out) {
+    if constexpr (Ar::kFixed) {
+        if (P.soft_q) {
+            // sat(R + L) at column m+1 (+-Q inside frozen CSFGs), as bytes
+            int8_t *so = P.soft_q + frame * N;
+            const float *Lm = Lc(M + 1);
+            for (int i = tid; i < N; i += NT)
+                so[i] = (int8_t)(int)(i < fm ? (((dw[i >> 6] >> (i & 63)) & 1) ? -big : big)
+                                             : Ar::sat(Rw[i] + Lm[i], P.qmax));
+        }
+    } else if (P.soft_out) {
         float *so = P.soft_out + frame * N;
         const float *Lm = Lc(M + 1);
         for (int i = tid; i < N; i += NT)
-            so[i] = i < fm ? (((dw[i >> 6] >> (i & 63)) & 1) ? -kInf : kInf)
+            so[i] = i < fm ? (((dw[i >> 6] >> (i & 63)) & 1) ? -big : big)
                            : Rw[i] + Lm[i];
     }
     if (tid == 0) {

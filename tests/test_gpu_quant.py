@@ -1,8 +1,8 @@
 """GPU parity of the fixed-point decoder (pbp_decode_quant) with the
 oracle's, through the C-ABI: decided bits, iteration counts, PE counts and
 the saturated posteriors all equal (integer arithmetic, so exact), in every
-mode and three message formats, for N = 2 to 4096 (every on-chip decoder
-and the byte-LDS kernel) including degenerate
+mode and three message formats, for N = 2 to 4096 (every decoder the
+lengths use) including degenerate
 rates and noiseless frames; the long-code limit is rejected."""
 
 import numpy as np
@@ -101,12 +101,12 @@ def test_quant_rejects(env):
                              bits=9)
 
 
-@pytest.mark.parametrize("N,K,B", [(64, 32, 200), (1024, 512, 40),
-                                   (4096, 2048, 6)])
+@pytest.mark.parametrize("N,K,B", [(64, 32, 200), (256, 128, 60),
+                                   (1024, 512, 40), (4096, 2048, 6)])
 def test_quant_alpha_above_one(env, N, K, B):
     """alpha = 1.25 (a = 20) with 8-bit messages: a scaled minimum reaches
-    (20 * 127 + 8) >> 4 = 159 > Q.  The oracle keeps it unsaturated, and the
-    on-chip decoders hold it exactly in FP32 registers."""
+    (20 * 127 + 8) >> 4 = 159 > Q.  The oracle keeps it unsaturated, and
+    every decoder holds it exactly in FP32 registers or LDS words."""
     pbp, torch = env
     fz = frozen_mask(N, K)
     _, _, llr = make_frames(N, K, B, 2.5, stream=1400 + N)
@@ -122,18 +122,6 @@ def test_quant_alpha_above_one(env, N, K, B):
         assert np.array_equal(got["pe"].cpu().numpy(), ref["pe"])
         assert np.array_equal(got["soft"].cpu().numpy().astype(np.int32),
                               ref["soft"])
-
-
-def test_quant_byte_format_limit(env):
-    """N = 128..512 keep each message as a byte in LDS: 8-bit messages with
-    alpha = 1.25 are rejected there; 7-bit ones fit at any alpha below 2."""
-    pbp, torch = env
-    code = pbp.Code(256, 128, frozen_mask(256, 128))
-    with pytest.raises(pbp.PbpError):
-        pbp.pbp_decode_quant(code, torch.zeros((1, 256), device="cuda"),
-                             bits=8, alpha=1.25)
-    pbp.pbp_decode_quant(code, torch.zeros((1, 256), device="cuda"), bits=7,
-                         alpha=1.25)
 
 
 def test_quant_unaligned_and_many_frames(env):
