@@ -23,10 +23,10 @@
 
 namespace {
 
+// the call's validated arguments, before they go to one decoder's parameters
 struct QParams {
     const float *llr;
     int64_t B;
-    const uint64_t *frozen_words;
     const int32_t *info_pos;
     int32_t K;
     int32_t max_iter, early_stop, freezing, freeze_input, freeze_walk;
@@ -261,7 +261,6 @@ extern "C" int32_t pbp_decode_quant(const pbp_code *code, const float *llr,
     QParams P{};
     P.llr = llr;
     P.B = B;
-    P.frozen_words = code->d_frozen_words;
     P.info_pos = code->d_info_pos;
     P.K = code->K;
     P.max_iter = opts->max_iter;

@@ -72,6 +72,7 @@ CASES = [
     (64, 32, 2.5, 400),
     (128, 64, 2.0, 200),
     (256, 85, 2.0, 100),
+    (512, 256, 2.5, 60),
     (1024, 512, 3.0, 160),
     (1024, 512, 1.5, 64),
     (2048, 1024, 2.5, 16),

@@ -55,7 +55,8 @@ def run(env, N, K, llr, bits, frac, mode):
 @pytest.mark.parametrize("mode", list(MODES))
 @pytest.mark.parametrize("N,K,ebn0,B", [(2, 1, 2.0, 100), (8, 4, 2.0, 100),
                                         (32, 16, 2.0, 200),
-                                        (64, 32, 2.5, 200), (256, 128, 2.5, 100),
+                                        (64, 32, 2.5, 200), (128, 64, 2.5, 100),
+                                        (256, 128, 2.5, 100), (512, 256, 2.5, 60),
                                         (1024, 512, 3.0, 60),
                                         (2048, 1024, 2.5, 12),
                                         (4096, 2048, 2.5, 8)])
