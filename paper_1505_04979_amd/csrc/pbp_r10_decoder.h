@@ -333,8 +333,8 @@ struct Decoder {
     // Lin = L at column J+1; the outputs L at column J go to registers, to
     // LDS (boundary column) or into the channel-side decisions (J = 1).
     // KEPT: stage M may read rows frozen at stage M (their kept decisions)
-    template <int J, int QA, bool KEPT>
-    __device__ __forceinline__ void pe_update()
+    template <int J, int QA, bool KEPT, bool MASKED = false>
+    __device__ __forceinline__ void pe_update(bool keep = true)
     {
         constexpr int MP = smap(J);
         constexpr int QB = QA | (1 << sqb(J));
@@ -359,12 +359,14 @@ struct Decoder {
                 X[QB] = ballot(Rb + lbv < 0.0f);
             }
         } else if constexpr (lbcol(J) >= 0) {
-            S.lb[lbcol(J)][lds_word<MP>(QA)] = la;
-            S.lb[lbcol(J)][lds_word<MP>(QB)] = lbv;
+            if (!MASKED || keep) {
+                S.lb[lbcol(J)][lds_word<MP>(QA)] = la;
+                S.lb[lbcol(J)][lds_word<MP>(QB)] = lbv;
+            }
         } else {
             float *Lout = lreg<J>();
-            Lout[QA] = la;
-            Lout[QB] = lbv;
+            Lout[QA] = (!MASKED || keep) ? la : Lout[QA];
+            Lout[QB] = (!MASKED || keep) ? lbv : Lout[QB];
         }
         // one PE at a time: dependent VALU operations issue back to back, so
         // interleaving PEs buys nothing but register pressure
@@ -395,8 +397,9 @@ struct Decoder {
         if constexpr (QA < Q) {
             if constexpr (!((QA >> sqb(J)) & 1) && slot_of<J>(QA) == SLOT) {
                 constexpr int MP = smap(J);
-                if (lr[MP] >= opaque_s(f - rowq(MP, QA)))
-                    pe_update<J, QA, KEPT>();
+                // R of rows below f is not read again in this sweep, so
+                // only the L outputs keep their old values there
+                pe_update<J, QA, KEPT, true>(lr[MP] >= opaque_s(f - rowq(MP, QA)));
             }
             pe_slot_masked<J, QA + 1, SLOT, KEPT>(f);
         }
