@@ -132,15 +132,16 @@ hipError_t launch_decode(const pbp_code *c, DecodeParams &P, float *state,
 template <int M>
 hipError_t launch_wave(DecodeParams &P, hipStream_t st)
 {
-    int64_t grid = P.B;
+    constexpr int W = pbp::wave::kWaves;
+    int64_t grid = (P.B + W - 1) / W;
     if (grid > (1ll << 30))
         grid = 1ll << 30;
     if (P.freezing)
         hipLaunchKernelGGL((pbp::wave::bp_decode_wave_kernel<M, true>),
-                           dim3((unsigned)grid), dim3(64), 0, st, P);
+                           dim3((unsigned)grid), dim3(64 * W), 0, st, P);
     else
         hipLaunchKernelGGL((pbp::wave::bp_decode_wave_kernel<M, false>),
-                           dim3((unsigned)grid), dim3(64), 0, st, P);
+                           dim3((unsigned)grid), dim3(64 * W), 0, st, P);
     return hipGetLastError();
 }
 

@@ -130,15 +130,16 @@ hipError_t launch_quant_wave(const pbp_code *c, const QParams &Q, float alpha_q,
                              hipStream_t st)
 {
     const pbp::generic::DecodeParams P = decode_params(c, Q, alpha_q);
-    int64_t grid = P.B;
+    constexpr int W = pbp::wave::kWaves;
+    int64_t grid = (P.B + W - 1) / W;
     if (grid > (1ll << 30))
         grid = 1ll << 30;
     if (P.freezing)
         hipLaunchKernelGGL((pbp::wave::bp_decode_wave_kernel<M, true, pbp::arith::Fixed>),
-                           dim3((unsigned)grid), dim3(64), 0, st, P);
+                           dim3((unsigned)grid), dim3(64 * W), 0, st, P);
     else
         hipLaunchKernelGGL((pbp::wave::bp_decode_wave_kernel<M, false, pbp::arith::Fixed>),
-                           dim3((unsigned)grid), dim3(64), 0, st, P);
+                           dim3((unsigned)grid), dim3(64 * W), 0, st, P);
     return hipGetLastError();
 }
 

@@ -4,7 +4,8 @@
 // error-rate reference of Section III's comparison of a frozen CSFG's ML
 // decision with SC.
 //
-// One wavefront per frame, persistent over a grid stride.  The node at
+// One wavefront per frame, persistent over a grid stride; a workgroup holds
+// up to four such wavefronts, each with its own LDS.  The node at
 // depth d of the SC tree covers 2^(m-d) consecutive source bits; its LLRs
 // live in LDS (alpha: depth d at offset N - 2^(m-d+1), 2^(m-d) values; the
 // channel LLRs of depth 0 are read in place).  The re-encoded bits of every
@@ -25,6 +26,24 @@
 #include "pbp_internal.h"
 
 namespace {
+
+// LDS of one wavefront: node LLRs (N floats) and re-encoded bits (N bytes)
+__host__ __device__ constexpr size_t lds_per_wave(int N)
+{
+    return (sizeof(float) * (size_t)N + (size_t)N + 15) & ~(size_t)15;
+}
+
+// Independent wavefronts per workgroup, each decoding its own frames in its
+// own LDS slice.  A compute unit holds at most 16 workgroups, so groups of
+// one wavefront would cap it at 16 wavefronts; up to four per group (within
+// 128 KB of LDS per group) let the register and LDS budgets set the
+// occupancy.
+template <int M>
+__host__ __device__ constexpr int sc_waves()
+{
+    return lds_per_wave(1 << M) * 4 <= 131072 ? 4
+         : lds_per_wave(1 << M) * 2 <= 131072 ? 2 : 1;
+}
 
 // f: the min-sum check-node rule sign(a) sign(b) min(|a|, |b|), exact (a
 // selection: b clamped to [-|a|, |a|] with the sign of a applied)
@@ -60,15 +79,20 @@ struct SCParams {
 
 // N < 64: every level in LDS
 template <int M>
-__global__ __launch_bounds__(64) void sc_decode_kernel(SCParams P)
+__global__ __launch_bounds__(64 * sc_waves<M>()) void sc_decode_kernel(SCParams P)
 {
     constexpr int N = 1 << M;
-    extern __shared__ __align__(16) unsigned char smem[];
+    extern __shared__ __align__(16) unsigned char smem_all[];
+    // each wavefront of the group decodes its own frames in its own LDS
+    const int wv = (int)threadIdx.x >> 6;
+    unsigned char *smem = smem_all + wv * lds_per_wave(N);
     float *alpha = reinterpret_cast<float *>(smem);          // N - 1 floats
     uint8_t *beta = smem + sizeof(float) * N;                // N bytes
-    const int lane = (int)threadIdx.x;
+    const int lane = (int)threadIdx.x & 63;
 
-    for (int64_t frame = blockIdx.x; frame < P.B; frame += gridDim.x) {
+    constexpr int W = sc_waves<M>();
+    for (int64_t frame = (int64_t)blockIdx.x * W + wv; frame < P.B;
+         frame += (int64_t)gridDim.x * W) {
         const float *ch = P.llr + frame * N;
         // depth d >= 1 starts at N - 2^(m-d+1); depth 0 is the channel
         auto col = [&](int d) -> float * { return alpha + (N - (N >> (d - 1))); };
@@ -116,9 +140,10 @@ __global__ __launch_bounds__(64) void sc_decode_kernel(SCParams P)
         }
         // beta now holds x = u G, the re-encoded word; the decided source
         // bits are its transform (G is its own inverse)
-        for (int h = 1; h < N; h <<= 1) {
+        for (int l = 0; (1 << l) < N; l++) {
+            const int h = 1 << l;
             for (int q = lane; q < N / 2; q += 64) {
-                const int a = ((q / h) * 2 * h) + (q % h);
+                const int a = ((q >> l) << (l + 1)) | (q & (h - 1));
                 beta[a] ^= beta[a + h];
             }
             wave_sync();
@@ -217,16 +242,21 @@ struct Sub64 {
 // N >= 64: the levels above the 64-position subtrees in LDS, the subtrees in
 // registers
 template <int M>
-__global__ __launch_bounds__(64) void sc_decode64_kernel(SCParams P)
+__global__ __launch_bounds__(64 * sc_waves<M>()) void sc_decode64_kernel(SCParams P)
 {
     constexpr int N = 1 << M;
     constexpr int MS = M - 6;                 // depth of the 64-position nodes
-    extern __shared__ __align__(16) unsigned char smem[];
+    extern __shared__ __align__(16) unsigned char smem_all[];
+    // each wavefront of the group decodes its own frames in its own LDS
+    const int wv = (int)threadIdx.x >> 6;
+    unsigned char *smem = smem_all + wv * lds_per_wave(N);
     float *alpha = reinterpret_cast<float *>(smem);          // N - 1 floats
     uint8_t *beta = smem + sizeof(float) * N;                // N bytes
-    const int lane = (int)threadIdx.x;
+    const int lane = (int)threadIdx.x & 63;
 
-    for (int64_t frame = blockIdx.x; frame < P.B; frame += gridDim.x) {
+    constexpr int W = sc_waves<M>();
+    for (int64_t frame = (int64_t)blockIdx.x * W + wv; frame < P.B;
+         frame += (int64_t)gridDim.x * W) {
         const float *ch = P.llr + frame * N;
         auto col = [&](int d) -> float * { return alpha + (N - (N >> (d - 1))); };
         for (int s = 0; s < (N >> 6); s++) {
@@ -272,9 +302,10 @@ __global__ __launch_bounds__(64) void sc_decode64_kernel(SCParams P)
             }
         }
         // beta holds x = u G; the decided source bits are its transform
-        for (int h = 1; h < N; h <<= 1) {
+        for (int l = 0; (1 << l) < N; l++) {
+            const int h = 1 << l;
             for (int q = lane; q < N / 2; q += 64) {
-                const int a = ((q / h) * 2 * h) + (q % h);
+                const int a = ((q >> l) << (l + 1)) | (q & (h - 1));
                 beta[a] ^= beta[a + h];
             }
             wave_sync();
@@ -289,8 +320,8 @@ __global__ __launch_bounds__(64) void sc_decode64_kernel(SCParams P)
 // as many wavefronts per compute unit as are resident (occ, looked up once
 // per kernel): a grid stride over more would leave the extra ones a tail
 template <class Kern>
-hipError_t launch_k(Kern kern, const pbp_code *c, SCParams &P, size_t lds,
-                    int &occ, hipStream_t st)
+hipError_t launch_k(Kern kern, const pbp_code *c, SCParams &P, int waves,
+                    size_t lds, int &occ, hipStream_t st)
 {
     hipError_t e = hipFuncSetAttribute((const void *)kern,
                                        hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -300,16 +331,16 @@ hipError_t launch_k(Kern kern, const pbp_code *c, SCParams &P, size_t lds,
     if (occ < 1) {
         int o = 0;
         e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&o, (const void *)kern,
-                                                         64, lds);
+                                                         64 * waves, lds);
         if (e != hipSuccess)
             return e;
         occ = o < 1 ? 1 : o;
     }
-    int64_t grid = P.B;
+    int64_t grid = (P.B + waves - 1) / waves;
     const int64_t cap = (int64_t)c->cus * occ;
     if (grid > cap)
         grid = cap;
-    hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(64), lds, st, P);
+    hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(64 * waves), lds, st, P);
     return hipGetLastError();
 }
 
@@ -317,12 +348,13 @@ template <int M>
 hipError_t launch_sc(const pbp_code *c, SCParams &P, hipStream_t st)
 {
     constexpr int N = 1 << M;
-    const size_t lds = sizeof(float) * N + N;
+    constexpr int W = sc_waves<M>();
+    const size_t lds = W * lds_per_wave(N);
     static int occ = 0;
     if constexpr (M >= 6)
-        return launch_k(sc_decode64_kernel<M>, c, P, lds, occ, st);
+        return launch_k(sc_decode64_kernel<M>, c, P, W, lds, occ, st);
     else
-        return launch_k(sc_decode_kernel<M>, c, P, lds, occ, st);
+        return launch_k(sc_decode_kernel<M>, c, P, W, lds, occ, st);
 }
 
 }  // namespace

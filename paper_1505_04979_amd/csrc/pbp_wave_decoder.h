@@ -25,12 +25,17 @@ namespace {
 // their decisions into one uniform word.  Rows below a stage's frozen prefix
 // keep their L (their R is not read again in the sweep).  The stop test is
 // the same parity over the whole word.
+// Wavefronts per workgroup, each decoding its own frames (a compute unit
+// holds at most 16 workgroups: groups of one wavefront would cap it at 16)
+constexpr int kWaves = 4;
+
 template <int M, bool FRZ, class Ar = arith::F32>
-__global__ __launch_bounds__(64) void bp_decode_wave_kernel(generic::DecodeParams P)
+__global__ __launch_bounds__(64 * kWaves) void bp_decode_wave_kernel(generic::DecodeParams P)
 {
     constexpr int N = 1 << M;
     static_assert(M >= 1 && M <= 6, "one row per lane");
-    const int lane = (int)__builtin_amdgcn_workitem_id_x();
+    const int lane = (int)__builtin_amdgcn_workitem_id_x() & 63;
+    const int wv = (int)__builtin_amdgcn_workitem_id_x() >> 6;
     const bool act = lane < N;
     const bool frz = act && ((P.frozen_words[0] >> lane) & 1);
     // lanes whose index contains this lane's index bits
@@ -50,7 +55,8 @@ __global__ __launch_bounds__(64) void bp_decode_wave_kernel(generic::DecodeParam
     const float big = Ar::big(P.qmax);      // inf, or Q in fixed point
     const float prior = frz ? big : 0.0f;
     const float alpha = P.alpha;
-    for (int64_t frame = blockIdx.x; frame < P.B; frame += gridDim.x) {
+    for (int64_t frame = (int64_t)blockIdx.x * kWaves + wv; frame < P.B;
+         frame += (int64_t)gridDim.x * kWaves) {
         const float ch = act ? Ar::channel(P.llr[frame * N + lane], P.frac, P.qmax) : 0.0f;
         float L[M + 1];                // L at columns 1..m+1 (index c - 1)
 #pragma unroll
