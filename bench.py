@@ -86,6 +86,8 @@ TRACE_RECORDS = {
 }
 COUNTER_RECORDS = {
     "n1024": ("counters_bp_decode_r10_n1024_3db.md", KERNEL_SRCS),
+    "unrolled": ("counters_unrolled_backward_n1024.md",
+                 TRAFFIC_RECORDS["unrolled"][1]),
 }
 
 MODES = {
@@ -1190,8 +1192,12 @@ def bench_unrolled(args, pbp, torch):
                   "kernel_ms": _round(traced_kernel_ms(
                       "unrolled", "unrolled_backward_kernel<10>", B), 4),
                   "event_ms": round(bwd_ms, 4),
+                  "valu_issue_frac": _round(valu_issue(
+                      "unrolled", "unrolled_backward_kernel<10>", B, bwd_ms), 4),
                   "note": "checkpoint reads (T x B x (m-1) x N x 4 B), LLR "
-                          "and output-gradient reads, gradient writes"},
+                          "and output-gradient reads, gradient writes; the "
+                          "kernel issues VALU at valu_issue_frac of the lane "
+                          "rate, which bounds it before HBM does"},
         forward_roofline={"bound": "hbm", "achieved": round(fwd_gbs, 1),
                           "peak": HBM_PEAK_GBS, "unit": "GB/s",
                           "frac": round(fwd_gbs / HBM_PEAK_GBS, 4),

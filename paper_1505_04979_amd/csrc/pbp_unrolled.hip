@@ -142,6 +142,56 @@ __device__ __forceinline__ void sync_wave_lds()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront", "local");
 }
 
+// v from the lane that DPP control CTRL names (a pattern inside each row of
+// 16 lanes, so every lane has a source)
+template <int CTRL>
+__device__ __forceinline__ float dpp_f(float v)
+{
+    return __int_as_float(
+        __builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+
+// v plus lane 15 of the previous row, in rows 1 and 3 (rows 0 and 2 keep v).
+// The s_nop gives the two wait states a DPP read of a VGPR needs after a
+// VALU write of it.
+__device__ __forceinline__ float add_bcast15(float v)
+{
+    asm("s_nop 1\n\tv_add_f32_dpp %0, %0, %0 row_bcast:15 row_mask:0xa bank_mask:0xf"
+        : "+v"(v));
+    return v;
+}
+
+// v plus lane 31, in rows 2 and 3 (rows 0 and 1 keep v)
+__device__ __forceinline__ float add_bcast31(float v)
+{
+    asm("s_nop 1\n\tv_add_f32_dpp %0, %0, %0 row_bcast:31 row_mask:0xc bank_mask:0xf"
+        : "+v"(v));
+    return v;
+}
+
+// Sums of a and b over the wavefront, complete in lane 63.  Within each row
+// of 16 lanes a butterfly by DPP (the lane i ^ 1, i ^ 2, then the mirrored
+// quad of the 8-lane half and the mirrored half of the row) leaves the row's
+// sum r in all its lanes; lane 15 of each row is then added into rows 1 and
+// 3, and lane 31 into rows 2 and 3, so lane 63 holds (r3 + r2) + (r1 + r0).
+// No LDS; the order is the same in every call.  The two sums are
+// interleaved so that each covers the other's DPP wait.
+__device__ __forceinline__ void wave_sum2(float &a, float &b)
+{
+    a += dpp_f<0xB1>(a);            // quad_perm [1, 0, 3, 2]
+    b += dpp_f<0xB1>(b);
+    a += dpp_f<0x4E>(a);            // quad_perm [2, 3, 0, 1]
+    b += dpp_f<0x4E>(b);
+    a += dpp_f<0x141>(a);           // row_half_mirror
+    b += dpp_f<0x141>(b);
+    a += dpp_f<0x140>(a);           // row_mirror
+    b += dpp_f<0x140>(b);
+    a = add_bcast15(a);
+    b = add_bcast15(b);
+    a = add_bcast31(a);
+    b = add_bcast31(b);
+}
+
 template <int NW>
 __device__ __forceinline__ void sync_stages(int h_first, int h_second)
 {
@@ -410,15 +460,11 @@ __global__ __launch_bounds__(Shape<M>::NT, 5) void unrolled_backward_kernel(BwdP
                     dRo[b] = dRb;
                 }
                 // this stage's scale gradients, summed over the wavefront
-                // (the group's sum is taken once per iteration); the shuffles
-                // overlap the next stage's load in flight
+                // (the group's sum is taken once per iteration)
                 {
                     float vL = daL, vR = daR;
-                    for (int o = 32; o >= 1; o >>= 1) {
-                        vL += __shfl_xor(vL, o, 64);
-                        vR += __shfl_xor(vR, o, 64);
-                    }
-                    if (lane == 0) {
+                    wave_sum2(vL, vR);
+                    if (lane == 63) {
                         red[((j - 1) * NW + wv) * 2] = vL;
                         red[((j - 1) * NW + wv) * 2 + 1] = vR;
                     }
