@@ -54,14 +54,14 @@ TRAFFIC_RECORDS = {
               _csrc("pbp_r10.hip", "pbp_r10_decoder.h", "pbp_r10.h",
                     "pbp_arith.h")),
     "n16384": ("traffic_bp_decode_n16384_2db.txt",
-               _csrc("pbp_decode.hip", "pbp_generic_decoder.h")),
+               _csrc("pbp_decode.hip", "pbp_generic_decoder.h", "pbp_lanes.h")),
     "unrolled": ("traffic_unrolled_backward_n1024.txt",
                  _csrc("pbp_unrolled.hip")),
     # the mixed batch's N = 4096 frames decoded alone: three class kernels
     # (one per rate) per decode, summed
     "mixed": ("traffic_class_pair_n4096_mixed.txt",
               _csrc("pbp_mixed.hip", "pbp_pair_decoder.h",
-                    "pbp_generic_decoder.h", "pbp_arith.h")),
+                    "pbp_generic_decoder.h", "pbp_arith.h", "pbp_lanes.h")),
 }
 KERNEL_SRCS = TRAFFIC_RECORDS["n1024"][1]
 
@@ -73,9 +73,8 @@ TRACE_RECORDS = {
     "n1024": ("bp_decode_r10_n1024_3db_trace.md", KERNEL_SRCS),
     "c1": ("bp_decode_n64_c1_trace.md",
            _csrc("pbp_decode.hip", "pbp_wave_decoder.h", "pbp_arith.h",
-                 "pbp_generic_decoder.h")),
-    "n16384": ("n16384_trace.md",
-               _csrc("pbp_decode.hip", "pbp_generic_decoder.h")),
+                 "pbp_generic_decoder.h", "pbp_lanes.h")),
+    "n16384": ("n16384_trace.md", TRAFFIC_RECORDS["n16384"][1]),
     "sc": ("sc_decode_n1024_trace.md", _csrc("pbp_sc.hip")),
     "quant": ("quant_decode_n1024_3db_trace.md",
               _csrc("pbp_quant.hip", "pbp_r10_decoder.h", "pbp_r10.h",

@@ -20,6 +20,7 @@
 #include <stdint.h>
 
 #include "pbp_arith.h"
+#include "pbp_lanes.h"
 #include "pbp_internal.h"
 
 namespace pbp {
@@ -55,13 +56,6 @@ __device__ __forceinline__ uint64_t ffx_word(uint64_t x)
     x ^= (x >> 16) & 0x0000FFFF0000FFFFull;
     x ^= (x >> 32) & 0x00000000FFFFFFFFull;
     return x;
-}
-
-__device__ __forceinline__ uint64_t shfl_xor64(uint64_t v, int mask)
-{
-    const int lo = __shfl_xor((int)(uint32_t)v, mask, 64);
-    const int hi = __shfl_xor((int)(uint32_t)(v >> 32), mask, 64);
-    return ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo;
 }
 
 // Order LDS traffic between the lanes of one wavefront.
@@ -113,10 +107,13 @@ __device__ __forceinline__ void pe_eq1(float La, float Lb, float Ra, float Rb,
 __device__ __forceinline__ void ffx_cross(uint64_t (&r)[kMaxWordsPerLane],
                                           int nw, int lane)
 {
-    for (int L = 1; L < nw && L < 64; L <<= 1) {
+#pragma unroll
+    for (int L = 1; L < 64; L <<= 1) {
+        if (L >= nw)
+            break;
 #pragma unroll
         for (int q = 0; q < kMaxWordsPerLane; q++) {
-            const uint64_t o = shfl_xor64(r[q], L);
+            const uint64_t o = lanes::down_u64(r[q], L);
             if (!(lane & L))
                 r[q] ^= o;
         }

@@ -40,6 +40,7 @@
 #include <stdint.h>
 
 #include "pbp_arith.h"
+#include "pbp_lanes.h"
 #include "pbp_generic_decoder.h"
 #include "pbp_internal.h"
 
@@ -53,7 +54,6 @@ using generic::ffx_cross;
 using generic::ffx_word;
 using generic::kBatch;
 using generic::kMaxWordsPerLane;
-using generic::shfl_xor64;
 
 template <int M>
 struct Shape {
@@ -369,7 +369,7 @@ struct Decoder {
         uint64_t x = in ? ffx_word(buf[lane]) : 0;
 #pragma unroll
         for (int L = 1; L < NB; L <<= 1) {
-            const uint64_t o = shfl_xor64(x, L);
+            const uint64_t o = lanes::down_u64(x, L);
             if (!(lane & L))
                 x ^= o;
         }
