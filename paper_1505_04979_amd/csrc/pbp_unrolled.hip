@@ -43,9 +43,10 @@ __device__ __forceinline__ float g0(float x, float y)
 
 __device__ __forceinline__ bool finite(float v) { return fabsf(v) < kInf; }
 
+// +-1 with the sign of v, 0 for +-0
 __device__ __forceinline__ float sgn(float v)
 {
-    return (float)((v > 0.0f) - (v < 0.0f));
+    return v == 0.0f ? 0.0f : __builtin_copysignf(1.0f, v);
 }
 
 // adjoint d of g(x, y) routed to x or y; an infinite operand takes nothing
@@ -407,7 +408,9 @@ __global__ __launch_bounds__(Shape<M>::NT, 5) void unrolled_backward_kernel(BwdP
                 const float aL = scale_at(P.alpha, ((int64_t)t * M + (j - 1)) * 2);
                 const float aR = scale_at(P.alpha, ((int64_t)t * M + (j - 1)) * 2 + 1);
                 const int sh = M - j, h = 1 << sh;
-                float daL = 0.0f, daR = 0.0f;
+                // sums start at -0, the identity of the addition (the first
+                // term is then taken as it is)
+                float daL = -0.0f, daR = -0.0f;
                 if (tid < H) {
                     const int a = row_a(j);
                     const int b = a + h;
@@ -441,7 +444,7 @@ __global__ __launch_bounds__(Shape<M>::NT, 5) void unrolled_backward_kernel(BwdP
                     const float dgA = aL * oLa;
                     const float dg1 = aL * oLb + aR * oRb;
                     const float dgB = aR * oRa;
-                    float dLa = 0.0f, dLb = oLb, dRa = 0.0f, dRb = oRb, ds = 0.0f;
+                    float dLa = -0.0f, dLb = oLb, dRa = -0.0f, dRb = oRb, ds = -0.0f;
                     g0_back(La, s, dgA, dLa, ds);
                     g0_back(La, Ra, dg1, dLa, dRa);
                     g0_back(Ra, s, dgB, dRa, ds);
