@@ -25,6 +25,34 @@ namespace {
 // their decisions into one uniform word.  Rows below a stage's frozen prefix
 // keep their L (their R is not read again in the sweep).  The stop test is
 // the same parity over the whole word.
+// This lane's two outputs of eq. (1) at a PE of stage j.  The PE joins rows
+// a and b = a + h; lane a (up false) keeps L_a and R_a, lane b (up true) L_b
+// and R_b.  Lin, R: this lane's L (column j+1) and R (column j); Lp, Rp: the
+// partner's.  Each output is the policy's own expression on the same
+// operands (so the results are those of Ar::pe), but only this row's two
+// are evaluated: the a row's term aLa clampm(La, .) is L_a at the a lane
+// and g1 at the b lane.
+template <class Ar>
+__device__ __forceinline__ void half_pe(bool up, float Lin, float Lp, float R,
+                                        float Rp, float alpha, float q,
+                                        float &oL, float &oR)
+{
+    const float La = up ? Lp : Lin;
+    const float aLa = arith::salpha(La, alpha);
+    if constexpr (Ar::kFixed) {
+        const float s = Ar::sat(Lp + Rp, q);            // a lane: Lb + Rb
+        const float t = Ar::term(aLa, La, up ? Rp : s); // g1, or L_a
+        oL = up ? Ar::sat(Lin + t, q) : t;
+        oR = up ? Ar::sat(R + t, q)
+                : Ar::term(arith::salpha(R, alpha), R, s);
+    } else {
+        const float s = Lp + Rp;                        // a lane: Lb + Rb
+        const float t = aLa * arith::clampm(La, up ? Rp : s);
+        oL = up ? Lin + t : t;
+        oR = up ? R + t : arith::salpha(R, alpha) * arith::clampm(R, s);
+    }
+}
+
 // Wavefronts per workgroup, each decoding its own frames (a compute unit
 // holds at most 16 workgroups: groups of one wavefront would cap it at 16)
 constexpr int kWaves = 4;
@@ -83,15 +111,13 @@ __global__ __launch_bounds__(64 * kWaves) void bp_decode_wave_kernel(generic::De
                 const float Lp = __shfl_xor(Lin, h, 64);
                 const float Rp = __shfl_xor(R, h, 64);
                 const bool up = (lane & h) != 0;
-                float oLa, oLb, oRa, oRb;
-                Ar::pe(up ? Lp : Lin, up ? Lin : Lp, up ? Rp : R, up ? R : Rp,
-                       alpha, P.qmax, oLa, oLb, oRa, oRb);
-                const float lo = up ? oLb : oLa;
+                float lo, ro;
+                half_pe<Ar>(up, Lin, Lp, R, Rp, alpha, P.qmax, lo, ro);
                 L[j - 1] = (!FRZ || lane >= f) ? lo : L[j - 1];
                 // channel-side decisions of the stop test: R + L at column 1
                 if (j == 1 && P.early_stop)
                     xw = __ballot(act && R + L[0] < 0.0f);
-                R = up ? oRb : oRa;
+                R = ro;
                 pe += (N - f) >> 1;
                 if constexpr (FRZ) {
                     // ---- CSFG walk at stage j (eqs. (2)-(4)) ----
