@@ -67,12 +67,15 @@ struct Fixed {
     {
         return sat(roundf(ldexpf(v, frac)), q);
     }
-    // t = (a/16) sign(x) clampm(x, y) is a multiple of 1/16 computed exactly,
-    // and trunc(t + copysign(1/2, t)) = sign(t) floor(|t| + 1/2)
-    __device__ static __forceinline__ float term(float sa, float x, float y)
+    // sign(x) sign(y) floor((a/16) min(|x|, |y|) + 1/2), a/16 the PE's scale
+    // (the argument a): the magnitude (a/16) min + 1/2 is a multiple of 1/32
+    // far below 2^24, so the fma is exact, and the sign bits of x and y are
+    // applied once to the rounded magnitude
+    __device__ static __forceinline__ float term(float a, float x, float y)
     {
-        const float t = sa * clampm(x, y);
-        return truncf(t + __builtin_copysignf(0.5f, t));
+        const float r = floorf(__builtin_fmaf(a, fminf(fabsf(x), fabsf(y)), 0.5f));
+        return __builtin_copysignf(
+            r, __uint_as_float(__float_as_uint(x) ^ __float_as_uint(y)));
     }
     // one PE of eq. (1): every sum saturates, the scaled minima do not
     __device__ static __forceinline__ void pe(float La, float Lb, float Ra, float Rb,
@@ -80,11 +83,10 @@ struct Fixed {
                                               float &lbv, float &ra, float &rb)
     {
         const float s = sat(Lb + Rb, q);
-        const float aLa = salpha(La, a);
-        const float g1 = term(aLa, La, Ra);
-        la = term(aLa, La, s);
+        const float g1 = term(a, La, Ra);
+        la = term(a, La, s);
         lbv = sat(Lb + g1, q);
-        ra = term(salpha(Ra, a), Ra, s);
+        ra = term(a, Ra, s);
         rb = sat(Rb + g1, q);
     }
 };

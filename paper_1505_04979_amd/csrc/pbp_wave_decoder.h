@@ -38,15 +38,14 @@ __device__ __forceinline__ void half_pe(bool up, float Lin, float Lp, float R,
                                         float &oL, float &oR)
 {
     const float La = up ? Lp : Lin;
-    const float aLa = arith::salpha(La, alpha);
     if constexpr (Ar::kFixed) {
-        const float s = Ar::sat(Lp + Rp, q);            // a lane: Lb + Rb
-        const float t = Ar::term(aLa, La, up ? Rp : s); // g1, or L_a
+        const float s = Ar::sat(Lp + Rp, q);             // a lane: Lb + Rb
+        const float t = Ar::term(alpha, La, up ? Rp : s); // g1, or L_a
         oL = up ? Ar::sat(Lin + t, q) : t;
-        oR = up ? Ar::sat(R + t, q)
-                : Ar::term(arith::salpha(R, alpha), R, s);
+        oR = up ? Ar::sat(R + t, q) : Ar::term(alpha, R, s);
     } else {
-        const float s = Lp + Rp;                        // a lane: Lb + Rb
+        const float aLa = arith::salpha(La, alpha);
+        const float s = Lp + Rp;                         // a lane: Lb + Rb
         const float t = aLa * arith::clampm(La, up ? Rp : s);
         oL = up ? Lin + t : t;
         oR = up ? R + t : arith::salpha(R, alpha) * arith::clampm(R, s);
