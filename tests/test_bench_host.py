@@ -110,3 +110,20 @@ def test_committed_records_match_the_kernel_sources():
         frames = int(lines["frames_per_launch"])
         assert bench.measured_traffic(name, frames) == float(
             lines["traffic_bytes_per_launch"]), name
+
+
+def test_committed_traces_and_counters_match_the_kernel_sources():
+    """Each kernel-trace and counter record was taken on the kernel sources
+    as they stand, so the benchmark lines carry the traced kernel time and
+    the VALU issue fraction (a kernel change needs a new trace)."""
+    for table in (bench.TRACE_RECORDS, bench.COUNTER_RECORDS):
+        for name, (record, srcs) in table.items():
+            path = os.path.join(ROOT, "profiles", record)
+            assert os.path.exists(path), (name, record)
+            lines = {ln[1:].split("=", 1)[0].strip(): ln.split("=", 1)[1].strip()
+                     for ln in open(path) if ln.startswith("@")}
+            assert lines["source_sha256_16"] == bench.source_digest(srcs), (name, record)
+            assert int(lines["frames_per_launch"]) > 0, (name, record)
+    assert bench.traced_kernel_ms("n1024", bench.KERNEL, 1000000) > 0
+    assert bench.valu_issue("n1024", bench.KERNEL, 1000000, 63.0) > 0
+    assert bench.valu_issue("unrolled", "unrolled_backward_kernel<10>", 4096, 1.4) > 0
